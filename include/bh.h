@@ -1,0 +1,176 @@
+/*
+ * bh.h -- C ABI of the MI355X ball-harmonic rotational-alignment library.
+ *
+ * Kruse, Kishore, Debarnot, Dokmanic, "Beyond Exhaustive Sampling: Efficient
+ * Rotational Matching via Ball Harmonics" (arXiv 2509.01180).
+ *
+ * The library computes, for a template t and a batch of subtomograms f,
+ * the rotation g maximising the zero-shift cross-correlation of Eq. (1),
+ *     C(g) = int t(x) [R_g f](x) dx,   (R_g f)(x) = f(g^{-1} x),
+ * through the ball-harmonic expansion (Sec. II-A) and the rotational
+ * correlation of Eq. (2), maximised by frequency marching and gradient
+ * ascent (Sec. II-C).
+ *
+ * Conventions (shared by every entry point)
+ * -----------------------------------------
+ * Volumes: N^3 FP32 samples on the cell-centred grid of [-1,1]^3,
+ *   x_i = (i - (N-1)/2) * 2/N, vols[b][i][j][k] = f_b(x_i, y_j, z_k)
+ *   (x slowest).  Only samples with |x| < 1 enter (the indicator of psi).
+ * Basis (Sec. II-A): psi_klm = c_lk j_l(lambda_lk r) Y_l^m(theta, phi),
+ *   lambda_lk the k-th zero of j_l, c_lk = sqrt(2)/|j_{l+1}(lambda_lk)|
+ *   (L2-orthonormal on the ball), Y_l^m complex orthonormal with the
+ *   Condon-Shortley phase.
+ * Band L: the frequency-ordered prefix {(k,l,m) : lambda_lk < lambda_{L+1,1}}.
+ * Coefficient layout: radial entries (l,k) in ascending lambda (ties by
+ *   (l,k)), each followed by m = -l..l; C(L) complex coefficients, stored
+ *   interleaved (re, im) as float[2*C].  bh_index_table lists the order.
+ * Coefficients: a_klm = h^3 sum_{|x_v|<1} conj(psi_klm(x_v)) f(x_v), h = 2/N
+ *   (voxel quadrature of the L2 inner product).
+ * Rotations: ZYZ Euler triples (alpha, beta, gamma), active,
+ *   R = R_z(alpha) R_y(beta) R_z(gamma); FP64.
+ * Cross-power (Eq. (2)): xi^l_{mn} = sum_{k in band} conj(b_klm) a_kln,
+ *   b = template, a = particle; score C(g) = Re sum_l sum_{mn} xi^l_{mn}
+ *   D^l_{mn}(g), D^l_{mn} = e^{-i m alpha} d^l_{mn}(beta) e^{-i n gamma},
+ *   d^l(beta) = exp(-i beta J_y).
+ *
+ * Memory: every pointer named "dev" is device memory owned by the caller;
+ * the library never frees caller memory.  A plan owns its basis matrix,
+ * tables and scratch.  All device work is enqueued on the caller's HIP
+ * stream (NULL = default stream) and is asynchronous; results are valid
+ * after the stream is synchronised.  A plan must not be used from two
+ * threads at once.
+ *
+ * Errors: every entry point returns BH_OK (0) or a negative code and sets a
+ * thread-local message readable with bh_last_error().  No C++ exception
+ * crosses this interface.  Kernel faults surface as BH_EDEVICE on a later
+ * call or at stream synchronisation.
+ */
+#ifndef BH_H
+#define BH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  BH_OK = 0,
+  BH_EINVAL = -1,        /* NULL pointer, size out of range, L > L_max   */
+  BH_ENOMEM = -2,        /* device or host allocation failed             */
+  BH_EDEVICE = -3,       /* HIP runtime error                            */
+  BH_EUNSUPPORTED = -4   /* shape outside the supported range            */
+};
+
+#define BH_MAX_L 64      /* largest bandlimit of any plan                 */
+#define BH_MAX_N 256     /* largest box edge of any plan                  */
+
+typedef struct bh_plan bh_plan;
+
+/* Last error message of the calling thread ("" if none). */
+const char* bh_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Host-only tables (no GPU needed).  Sec. II-A: index set and zeros.
+ * ------------------------------------------------------------------- */
+
+/* C(L): number of complex coefficients of band L (all m); <0 on error. */
+int64_t bh_index_size(int L);
+
+/* Per-coefficient table of band L, host arrays of length C(L), any may be
+ * NULL: degree l, radial index k (1-based), order m, and lambda_lk. */
+int bh_index_table(int L, int32_t* l, int32_t* k, int32_t* m, double* lambda);
+
+/* Number of radial entries (l,k) of band L; <0 on error. */
+int bh_radial_count(int L);
+
+/* Per-radial-entry table of band L in coefficient order, host arrays of
+ * length bh_radial_count(L), any may be NULL: l, k, lambda_lk, c_lk. */
+int bh_radial_table(int L, int32_t* l, int32_t* k, double* lambda, double* c);
+
+/* Number of cell-centred voxels strictly inside the unit ball, N^3 grid. */
+int64_t bh_ball_voxels(int N);
+
+/* ---------------------------------------------------------------------
+ * Plans
+ * ------------------------------------------------------------------- */
+
+/* Build the plan for box edge N (2..BH_MAX_N) and bandlimit L_max
+ * (0..BH_MAX_L) on HIP device `device`: host tables, then the basis matrix
+ * (h^3 conj(psi) at ball voxels, FP32, about 4*V_ball*C(L_max) bytes) on the
+ * device.  Synchronous.  *out is NULL on error. */
+int bh_plan_create(int N, int L_max, int device, bh_plan** out);
+
+/* Release a plan and its device memory (NULL is accepted).  Synchronises
+ * the device first. */
+void bh_plan_destroy(bh_plan* p);
+
+/* Complex coefficient count of the plan's band L (0 <= L <= L_max). */
+int64_t bh_plan_num_coeffs(const bh_plan* p, int L);
+
+/* ---------------------------------------------------------------------
+ * Expansion (Sec. II-A): volumes -> coefficients of band L_max.
+ * vols:   dev float[B][N][N][N]
+ * coeffs: dev float[B][C(L_max)][2]
+ * B >= 0 (B == 0 is a no-op).
+ * ------------------------------------------------------------------- */
+int bh_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Cross-power of Eq. (2) for band L (0 <= L <= L_max).
+ * a:  dev float[B][C(L_max)][2]  particle coefficients
+ * b:  dev float[C(L_max)][2]     template coefficients
+ * xi: dev double[B][E(L)][2], E(L) = sum_{l<=L} (2l+1)^2; block l is
+ *     row-major [m][n], m, n = -l..l, blocks in increasing l.
+ * ------------------------------------------------------------------- */
+int bh_cross_power(bh_plan* p, const float* a, const float* b, int64_t B, int L,
+                   double* xi, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Score and Euler gradient of Eq. (2) for band L at R rotations per
+ * particle (Sec. II-B, II-C).
+ * euler: dev double[B][R][3]
+ * score: dev double[B][R]
+ * grad:  dev double[B][R][3] (d/dalpha, d/dbeta, d/dgamma) or NULL
+ * 1 <= R <= 1<<20.
+ * ------------------------------------------------------------------- */
+int bh_correlate(bh_plan* p, const float* a, const float* b, int64_t B, int L,
+                 const double* euler, int R, double* score, double* grad, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Alignment (Sec. II-C): frequency marching over `bands` with multi-start
+ * gradient ascent.  For each band L_b (each <= L_max, any order): evaluate
+ * (S, grad S) at the carried point x; step eta = step_init / W_b with
+ * W_b = sum_{l<=L_b} l(l+1) ||a_l|| ||b_l|| over the band (0 if W_b = 0);
+ * then `steps_per_band` times: x' = wrap(x + eta * G^{-1}(x) grad S(x)),
+ * G the SO(3) metric in ZYZ coordinates with sin^2(beta) floored at 1e-6;
+ * accept x' if S(x') >= S(x) (eta *= step_grow) else eta *= step_shrink.
+ * wrap: beta into [0, pi] via R(a, b, g) = R(a + pi, 2pi - b, g + pi),
+ * alpha and gamma into [-pi, pi).  The best restart (highest final score,
+ * lowest index on ties) is returned.
+ * starts:    dev double[B][n_restarts][3]   starting Euler triples
+ * euler_out: dev double[B][3]
+ * score_out: dev double[B]
+ * all_euler: dev double[B][n_restarts][3] final point of every restart, or NULL
+ * all_score: dev double[B][n_restarts] its score, or NULL
+ * ------------------------------------------------------------------- */
+typedef struct {
+  const int32_t* bands;     /* host array of n_bands bandlimits           */
+  int32_t n_bands;          /* 1..16                                      */
+  int32_t steps_per_band;   /* 0..10000                                   */
+  int32_t n_restarts;       /* 1..65536                                   */
+  double step_init;         /* > 0                                        */
+  double step_grow;         /* > 0                                        */
+  double step_shrink;       /* > 0                                        */
+} bh_align_opts;
+
+int bh_align(bh_plan* p, const float* a, const float* b, int64_t B,
+             const bh_align_opts* opts, const double* starts,
+             double* euler_out, double* score_out,
+             double* all_euler, double* all_score, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BH_H */

@@ -17,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 from scipy import special
 
-from .basis import IndexSet, grid, spherical, sph_harm
+from .basis import IndexSet, grid, spherical
 
 
 def expand(vols: np.ndarray, idx: IndexSet) -> np.ndarray:
@@ -34,15 +34,16 @@ def expand(vols: np.ndarray, idx: IndexSet) -> np.ndarray:
     r, th, ph = spherical(xyz[ball])
     F = v.reshape(v.shape[0], -1)[:, ball.reshape(-1)].astype(np.complex128)
     out = np.zeros((v.shape[0], idx.size), dtype=np.complex128)
-    for l in sorted({e[0] for e in idx.radial}):
-        Y = np.stack([sph_harm(l, m, th, ph) for m in range(-l, l + 1)],
-                     axis=1)                                  # [V, 2l+1]
-        for (ll, _k, lam, c), off in zip(idx.radial, idx.offset):
-            if ll != l:
-                continue
-            rad = c * special.spherical_jn(l, lam * r)        # [V]
-            basis_conj = np.conj(rad[:, None] * Y)            # conj(psi)
-            out[:, off:off + 2 * l + 1] = (h ** 3) * (F @ basis_conj)
+    # Y_l^m at every ball voxel, all l <= L and |m| <= L (SciPy's recurrence);
+    # Yall[l, m] with negative m at negative indices.
+    Yall = special.sph_harm_y_all(idx.L, idx.L, th, ph)
+    # j_l(lambda r) only depends on r, which takes few distinct values on the grid.
+    r_unique, r_inverse = np.unique(r, return_inverse=True)
+    for (l, _k, lam, c), off in zip(idx.radial, idx.offset):
+        rad = (c * special.spherical_jn(l, lam * r_unique))[r_inverse]      # [V]
+        Y = Yall[l][np.arange(-l, l + 1)].T                                 # [V, 2l+1]
+        basis_conj = np.conj(rad[:, None] * Y)                              # conj(psi)
+        out[:, off:off + 2 * l + 1] = (h ** 3) * (F @ basis_conj)
     return out[0] if single else out
 
 

@@ -1,0 +1,85 @@
+"""ctypes loader of libbh.so (the C ABI declared in include/bh.h).
+
+The shared library is built in-tree by ``paper_2509_01180_amd.build``.  There
+is no fallback: if the library is missing or fails to load, every call
+raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbh.so")
+
+BH_OK, BH_EINVAL, BH_ENOMEM, BH_EDEVICE, BH_EUNSUPPORTED = 0, -1, -2, -3, -4
+BH_MAX_L = 64
+BH_MAX_N = 256
+
+
+class BhError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+class AlignOpts(ctypes.Structure):
+    _fields_ = [
+        ("bands", ctypes.POINTER(ctypes.c_int32)),
+        ("n_bands", ctypes.c_int32),
+        ("steps_per_band", ctypes.c_int32),
+        ("n_restarts", ctypes.c_int32),
+        ("step_init", ctypes.c_double),
+        ("step_grow", ctypes.c_double),
+        ("step_shrink", ctypes.c_double),
+    ]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_pI32 = ctypes.POINTER(ctypes.c_int32)
+_pF64 = ctypes.POINTER(ctypes.c_double)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "bh_last_error": (ctypes.c_char_p, []),
+    "bh_index_size": (_I64, [_I]),
+    "bh_index_table": (_I, [_I, _pI32, _pI32, _pI32, _pF64]),
+    "bh_radial_count": (_I, [_I]),
+    "bh_radial_table": (_I, [_I, _pI32, _pI32, _pF64, _pF64]),
+    "bh_ball_voxels": (_I64, [_I]),
+    "bh_plan_create": (_I, [_I, _I, _I, ctypes.POINTER(_P)]),
+    "bh_plan_destroy": (None, [_P]),
+    "bh_plan_num_coeffs": (_I64, [_P, _I]),
+    "bh_expand": (_I, [_P, _P, _I64, _P, _P]),
+    "bh_cross_power": (_I, [_P, _P, _P, _I64, _I, _P, _P]),
+    "bh_correlate": (_I, [_P, _P, _P, _I64, _I, _P, _I, _P, _P, _P]),
+    "bh_align": (_I, [_P, _P, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2509_01180_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code: int, where: str) -> int:
+    if code < 0:
+        msg = lib().bh_last_error().decode(errors="replace")
+        raise BhError(int(code), where, msg)
+    return code

@@ -1,0 +1,172 @@
+"""Python binding of the C ABI (include/bh.h) on torch tensors.
+
+Argument marshalling only: shapes and dtypes are checked, device pointers
+and the current HIP stream are handed to libbh, and every computation runs
+in the library's kernels.  Torch provides device memory and streams.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from ._lib import AlignOpts, check, lib
+
+__all__ = ["Plan", "index_size", "index_table", "radial_table", "ball_voxels",
+           "dense_xi_size"]
+
+
+def index_size(L: int) -> int:
+    """C(L): number of complex coefficients of band L."""
+    return check(lib().bh_index_size(int(L)), "bh_index_size")
+
+
+def index_table(L: int):
+    """Per-coefficient (l, k, m, lambda_lk) arrays of band L (host)."""
+    n = index_size(L)
+    l = np.zeros(n, np.int32)
+    k = np.zeros(n, np.int32)
+    m = np.zeros(n, np.int32)
+    lam = np.zeros(n, np.float64)
+    check(lib().bh_index_table(int(L), _i32(l), _i32(k), _i32(m), _f64(lam)), "bh_index_table")
+    return l, k, m, lam
+
+
+def radial_table(L: int):
+    """Per-radial-entry (l, k, lambda_lk, c_lk) arrays of band L (host)."""
+    n = check(lib().bh_radial_count(int(L)), "bh_radial_count")
+    l = np.zeros(n, np.int32)
+    k = np.zeros(n, np.int32)
+    lam = np.zeros(n, np.float64)
+    c = np.zeros(n, np.float64)
+    check(lib().bh_radial_table(int(L), _i32(l), _i32(k), _f64(lam), _f64(c)), "bh_radial_table")
+    return l, k, lam, c
+
+
+def ball_voxels(N: int) -> int:
+    return check(lib().bh_ball_voxels(int(N)), "bh_ball_voxels")
+
+
+def dense_xi_size(L: int) -> int:
+    """E(L) = sum_{l<=L} (2l+1)^2."""
+    return (L + 1) * (4 * (L + 1) ** 2 - 1) // 3
+
+
+def _i32(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _f64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, shape, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Plan:
+    """A basis plan for box edge N and bandlimit L_max on one GPU."""
+
+    def __init__(self, N: int, L_max: int, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.N, self.L_max, self.device = int(N), int(L_max), int(device)
+        h = ctypes.c_void_p()
+        check(lib().bh_plan_create(self.N, self.L_max, self.device, ctypes.byref(h)),
+              "bh_plan_create")
+        self._h = h
+        self.C = self.num_coeffs(self.L_max)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().bh_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_coeffs(self, L: int) -> int:
+        return check(lib().bh_plan_num_coeffs(self._h, int(L)), "bh_plan_num_coeffs")
+
+    # ----------------------------------------------------------- calls --
+    def expand(self, vols: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """vols [B, N, N, N] float32 -> coefficients [B, C(L_max), 2] float32."""
+        B = vols.shape[0]
+        _dev(vols, torch.float32, (B, self.N, self.N, self.N), "vols")
+        if out is None:
+            out = torch.empty((B, self.C, 2), dtype=torch.float32, device=vols.device)
+        _dev(out, torch.float32, (B, self.C, 2), "out")
+        check(lib().bh_expand(self._h, _ptr(vols), B, _ptr(out), _stream()), "bh_expand")
+        return out
+
+    def cross_power(self, a: torch.Tensor, b: torch.Tensor, L: int) -> torch.Tensor:
+        """xi [B, E(L), 2] float64 (blocks l, row-major [m][n])."""
+        B = a.shape[0]
+        _dev(a, torch.float32, (B, self.C, 2), "a")
+        _dev(b, torch.float32, (self.C, 2), "b")
+        out = torch.empty((B, dense_xi_size(L), 2), dtype=torch.float64, device=a.device)
+        check(lib().bh_cross_power(self._h, _ptr(a), _ptr(b), B, int(L), _ptr(out), _stream()),
+              "bh_cross_power")
+        return out
+
+    def correlate(self, a: torch.Tensor, b: torch.Tensor, L: int, euler: torch.Tensor,
+                  grad: bool = True):
+        """Score [B, R] and Euler gradient [B, R, 3] (float64) at euler [B, R, 3]."""
+        B = a.shape[0]
+        R = euler.shape[1]
+        _dev(a, torch.float32, (B, self.C, 2), "a")
+        _dev(b, torch.float32, (self.C, 2), "b")
+        _dev(euler, torch.float64, (B, R, 3), "euler")
+        score = torch.empty((B, R), dtype=torch.float64, device=a.device)
+        g = torch.empty((B, R, 3), dtype=torch.float64, device=a.device) if grad else None
+        check(lib().bh_correlate(self._h, _ptr(a), _ptr(b), B, int(L), _ptr(euler), R,
+                                 _ptr(score), _ptr(g), _stream()), "bh_correlate")
+        return score, g
+
+    def align(self, a: torch.Tensor, b: torch.Tensor, bands: Sequence[int], starts: torch.Tensor,
+              steps: int, step_init: float = 1.0, step_grow: float = 1.25,
+              step_shrink: float = 0.5, return_all: bool = False):
+        """Best rotation per particle: (euler [B, 3], score [B]) float64.
+
+        With return_all, also the final point [B, P, 3] and score [B, P] of
+        every restart.
+        """
+        B = a.shape[0]
+        P = starts.shape[1]
+        _dev(a, torch.float32, (B, self.C, 2), "a")
+        _dev(b, torch.float32, (self.C, 2), "b")
+        _dev(starts, torch.float64, (B, P, 3), "starts")
+        bl = (ctypes.c_int32 * len(bands))(*[int(x) for x in bands])
+        o = AlignOpts(ctypes.cast(bl, ctypes.POINTER(ctypes.c_int32)), len(bands), int(steps), P,
+                      float(step_init), float(step_grow), float(step_shrink))
+        eu = torch.empty((B, 3), dtype=torch.float64, device=a.device)
+        sc = torch.empty((B,), dtype=torch.float64, device=a.device)
+        ae = torch.empty((B, P, 3), dtype=torch.float64, device=a.device) if return_all else None
+        asc = torch.empty((B, P), dtype=torch.float64, device=a.device) if return_all else None
+        check(lib().bh_align(self._h, _ptr(a), _ptr(b), B, ctypes.byref(o), _ptr(starts),
+                             _ptr(eu), _ptr(sc), _ptr(ae), _ptr(asc), _stream()), "bh_align")
+        if return_all:
+            return eu, sc, ae, asc
+        return eu, sc

@@ -1,0 +1,295 @@
+// C ABI entry points (include/bh.h): argument checking, plan lifetime,
+// device selection and dispatch to the kernel launchers.
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "bh_internal.h"
+
+namespace bh {
+
+namespace {
+thread_local std::string g_err;
+
+// Make the plan's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return set_error(BH_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_error(BH_EINVAL, e.what());
+  } catch (...) {
+    return set_error(BH_EINVAL, "unknown error");
+  }
+}
+
+void free_band(DevBand& b) {
+  for (void* q : {(void*)b.rec, (void*)b.sel, (void*)b.wt, (void*)b.p_first, (void*)b.deg_start,
+                  (void*)b.deg_off})
+    if (q) (void)hipFree(q);
+  b = DevBand();
+}
+
+template <typename T>
+int upload_vec(const std::vector<T>& h, T** d) {
+  *d = nullptr;
+  const size_t n = h.empty() ? 1 : h.size();
+  BH_HIP(hipMalloc((void**)d, n * sizeof(T)));
+  if (!h.empty()) BH_HIP(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return BH_OK;
+}
+
+int check_L(int L) {
+  if (L < 0 || L > BH_MAX_L) return set_error(BH_EINVAL, "bandlimit out of range");
+  return BH_OK;
+}
+
+}  // namespace
+
+int set_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int grow(Buffer& b, size_t bytes) {
+  if (bytes <= b.bytes) return BH_OK;
+  if (b.ptr) {
+    BH_HIP(hipDeviceSynchronize());
+    BH_HIP(hipFree(b.ptr));
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  if (hipMalloc(&b.ptr, bytes) != hipSuccess) {
+    b.ptr = nullptr;
+    (void)hipGetLastError();
+    return set_error(BH_ENOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return BH_OK;
+}
+
+int get_band(bh_plan* p, int L, const DevBand** out) {
+  auto it = p->bands.find(L);
+  if (it != p->bands.end()) {
+    *out = &it->second;
+    return BH_OK;
+  }
+  BandTables t = band_tables(L, p->L_max);
+  t.rec.resize(t.rec.size() + 2 * kTablePad, 0.0);   // look-ahead padding
+  DevBand d;
+  d.L = L;
+  d.n_classes = t.n_classes;
+  d.n_entries = t.n_entries;
+  int rc;
+  if ((rc = upload_vec(t.rec, &d.rec)) != BH_OK ||
+      (rc = upload_vec(t.sel, &d.sel)) != BH_OK ||
+      (rc = upload_vec(t.wt, &d.wt)) != BH_OK ||
+      (rc = upload_vec(t.p_first, &d.p_first)) != BH_OK ||
+      (rc = upload_vec(t.deg_start, &d.deg_start)) != BH_OK ||
+      (rc = upload_vec(t.deg_off, &d.deg_off)) != BH_OK) {
+    free_band(d);
+    return rc;
+  }
+  p->bands[L] = d;
+  *out = &p->bands[L];
+  return BH_OK;
+}
+
+}  // namespace bh
+
+using namespace bh;
+
+extern "C" {
+
+const char* bh_last_error(void) { return g_err.c_str(); }
+
+int64_t bh_index_size(int L) {
+  if (check_L(L) != BH_OK) return BH_EINVAL;
+  try {
+    return index_set(L).C;
+  } catch (...) {
+    return set_error(BH_ENOMEM, "host allocation failed");
+  }
+}
+
+int bh_index_table(int L, int32_t* l, int32_t* k, int32_t* m, double* lambda) {
+  return guarded([&]() -> int {
+    int rc = check_L(L);
+    if (rc != BH_OK) return rc;
+    const IndexSet& s = index_set(L);
+    for (const Radial& r : s.rad)
+      for (int mm = -r.l; mm <= r.l; ++mm) {
+        const int q = r.offset + r.l + mm;
+        if (l) l[q] = r.l;
+        if (k) k[q] = r.k;
+        if (m) m[q] = mm;
+        if (lambda) lambda[q] = r.lam;
+      }
+    return BH_OK;
+  });
+}
+
+int bh_radial_count(int L) {
+  return guarded([&]() -> int {
+    int rc = check_L(L);
+    if (rc != BH_OK) return rc;
+    return (int)index_set(L).rad.size();
+  });
+}
+
+int bh_radial_table(int L, int32_t* l, int32_t* k, double* lambda, double* c) {
+  return guarded([&]() -> int {
+    int rc = check_L(L);
+    if (rc != BH_OK) return rc;
+    const IndexSet& s = index_set(L);
+    for (size_t i = 0; i < s.rad.size(); ++i) {
+      if (l) l[i] = s.rad[i].l;
+      if (k) k[i] = s.rad[i].k;
+      if (lambda) lambda[i] = s.rad[i].lam;
+      if (c) c[i] = s.rad[i].c;
+    }
+    return BH_OK;
+  });
+}
+
+int64_t bh_ball_voxels(int N) {
+  if (N < 1 || N > BH_MAX_N) return set_error(BH_EINVAL, "box edge out of range");
+  try {
+    return (int64_t)ball_voxels(N).size();
+  } catch (...) {
+    return set_error(BH_ENOMEM, "host allocation failed");
+  }
+}
+
+int bh_plan_create(int N, int L_max, int device, bh_plan** out) {
+  if (!out) return set_error(BH_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (N < 2 || N > BH_MAX_N) return set_error(BH_EINVAL, "box edge out of range");
+  if (L_max < 0 || L_max > BH_MAX_L) return set_error(BH_EINVAL, "bandlimit out of range");
+  return guarded([&]() -> int {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+      return set_error(BH_EDEVICE, "no HIP device");
+    if (device < 0 || device >= ndev) return set_error(BH_EINVAL, "device index out of range");
+    DeviceGuard g(device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    bh_plan* p = new bh_plan();
+    p->N = N;
+    p->L_max = L_max;
+    p->device = device;
+    p->idx = &index_set(L_max);
+    for (int L = 0; L <= L_max; ++L) p->band_size.push_back(index_set(L).C);
+    int rc = build_basis(p);
+    if (rc != BH_OK) {
+      bh_plan_destroy(p);
+      return rc;
+    }
+    *out = p;
+    return BH_OK;
+  });
+}
+
+void bh_plan_destroy(bh_plan* p) {
+  if (!p) return;
+  DeviceGuard g(p->device);
+  (void)hipDeviceSynchronize();
+  for (void* q : {(void*)p->psi, (void*)p->vidx, (void*)p->csrc, (void*)p->csgn})
+    if (q) (void)hipFree(q);
+  for (Buffer* b : {&p->gathered, &p->partial, &p->xi_scr, &p->state_scr, &p->misc_scr})
+    if (b->ptr) (void)hipFree(b->ptr);
+  for (auto& kv : p->bands) free_band(kv.second);
+  delete p;
+}
+
+int64_t bh_plan_num_coeffs(const bh_plan* p, int L) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (L < 0 || L > p->L_max) return set_error(BH_EINVAL, "L outside 0..L_max");
+  return p->band_size[L];
+}
+
+int bh_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (B < 0 || B > (1LL << 21)) return set_error(BH_EINVAL, "batch size out of range");
+  if (B == 0) return BH_OK;
+  if (!vols || !coeffs) return set_error(BH_EINVAL, "NULL buffer");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    return launch_expand(p, vols, B, coeffs, (hipStream_t)stream);
+  });
+}
+
+int bh_cross_power(bh_plan* p, const float* a, const float* b, int64_t B, int L, double* xi,
+                   void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (L < 0 || L > p->L_max) return set_error(BH_EINVAL, "L outside 0..L_max");
+  if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
+  if (B == 0) return BH_OK;
+  if (!a || !b || !xi) return set_error(BH_EINVAL, "NULL buffer");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    const DevBand* band = nullptr;
+    int rc = get_band(p, L, &band);
+    if (rc != BH_OK) return rc;
+    return launch_cross_power_dense(p, *band, a, b, B, xi, (hipStream_t)stream);
+  });
+}
+
+int bh_correlate(bh_plan* p, const float* a, const float* b, int64_t B, int L, const double* euler,
+                 int R, double* score, double* grad, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (L < 0 || L > p->L_max) return set_error(BH_EINVAL, "L outside 0..L_max");
+  if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
+  if (R < 1 || R > (1 << 20)) return set_error(BH_EINVAL, "rotation count out of range");
+  if (B == 0) return BH_OK;
+  if (!a || !b || !euler || !score) return set_error(BH_EINVAL, "NULL buffer");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    const DevBand* band = nullptr;
+    int rc = get_band(p, L, &band);
+    if (rc != BH_OK) return rc;
+    return launch_correlate(p, *band, a, b, B, euler, R, score, grad, (hipStream_t)stream);
+  });
+}
+
+int bh_align(bh_plan* p, const float* a, const float* b, int64_t B, const bh_align_opts* o,
+             const double* starts, double* euler_out, double* score_out, double* all_euler,
+             double* all_score, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (!o) return set_error(BH_EINVAL, "opts is NULL");
+  if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
+  if (o->n_bands < 1 || o->n_bands > 16 || !o->bands) return set_error(BH_EINVAL, "bad band list");
+  for (int i = 0; i < o->n_bands; ++i)
+    if (o->bands[i] < 0 || o->bands[i] > p->L_max) return set_error(BH_EINVAL, "band outside 0..L_max");
+  if (o->steps_per_band < 0 || o->steps_per_band > 10000) return set_error(BH_EINVAL, "bad step count");
+  if (o->n_restarts < 1 || o->n_restarts > 65536) return set_error(BH_EINVAL, "bad restart count");
+  if (!(o->step_init > 0) || !(o->step_grow > 0) || !(o->step_shrink > 0))
+    return set_error(BH_EINVAL, "step parameters must be positive");
+  if (B == 0) return BH_OK;
+  if (!a || !b || !starts || !euler_out || !score_out) return set_error(BH_EINVAL, "NULL buffer");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    return launch_align(p, a, b, B, *o, starts, euler_out, score_out, all_euler, all_score,
+                        (hipStream_t)stream);
+  });
+}
+
+}  // extern "C"

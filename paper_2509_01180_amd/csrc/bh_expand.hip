@@ -1,0 +1,170 @@
+// Expansion (Sec. II-A): a[b][c] = sum_v F[b][v] Psi[v][c], the voxel
+// quadrature of <f, psi_klm> as one dense real GEMM on MFMA, then the
+// complex coefficients of every m are rebuilt from the real columns.
+//
+//   k_gather  : volumes [B][N^3] -> Ft[V_pad][M_pad] (ball voxels, transposed,
+//               zero padded), so both GEMM operands are K-major.
+//   k_gemm_f32: split-K GEMM on v_mfma_f32_32x32x2f32, 128x128 tiles,
+//               K step 32, LDS double buffer; partial sums per split.
+//   k_reduce  : sums the splits in a fixed order and writes the complex
+//               layout (re, im) for m = -l..l.
+#include "bh_internal.h"
+
+namespace bh {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
+
+// Ft[v][b] = vols[b][vidx[v]] (0 outside v < V, b < B).  32x32 LDS transpose.
+__global__ __launch_bounds__(256) void k_gather(const float* __restrict__ vols, int64_t vol_stride,
+                                                int64_t B, const int32_t* __restrict__ vidx,
+                                                int64_t V, int64_t M_pad, float* __restrict__ Ft) {
+  __shared__ float tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  const int64_t v0 = (int64_t)blockIdx.x * 32, b0 = (int64_t)blockIdx.y * 32;
+  const int64_t v = v0 + tx;
+  const int32_t lin = (v < V) ? vidx[v] : 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t b = b0 + ty + 8 * i;
+    tile[ty + 8 * i][tx] = (v < V && b < B) ? vols[b * vol_stride + lin] : 0.0f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t vv = v0 + ty + 8 * i;
+    Ft[vv * M_pad + b0 + tx] = tile[tx][ty + 8 * i];
+  }
+}
+
+// part[s][m][n] = sum_{k in split s} Ft[k][m] Psi[k][n].
+// 4 waves in a 2x2 arrangement, each 64x64 = 2x2 MFMA 32x32 tiles.
+// MFMA 32x32x2 f32 operand layout: lane L supplies A[L%32][L/32] and
+// B[L/32][L%32]; accumulator r of lane L is D[8(r/4) + 4(L/32) + r%4][L%32].
+__global__ __launch_bounds__(256, 2) void k_gemm_f32(const float* __restrict__ Ft,
+                                                     const float* __restrict__ Psi,
+                                                     float* __restrict__ part, int64_t M_pad,
+                                                     int64_t C_pad, int nk) {
+  __shared__ float As[2][BK][BM];
+  __shared__ float Bs[2][BK][BN];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const int64_t k_begin = (int64_t)blockIdx.z * nk * BK;
+  const int lr = tid >> 5, lc = (tid & 31) * 4;
+  const float* pa = Ft + (k_begin + lr) * M_pad + m0 + lc;
+  const float* pb = Psi + (k_begin + lr) * C_pad + n0 + lc;
+  const int64_t sa = 8 * M_pad, sb = 8 * C_pad;          // 8 rows apart
+  const int64_t stepa = BK * M_pad, stepb = BK * C_pad;  // one K step
+  float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define BH_GLOAD(kt)                                                        \
+  do {                                                                      \
+    const float* qa = pa + (int64_t)(kt) * stepa;                           \
+    const float* qb = pb + (int64_t)(kt) * stepb;                           \
+    ra0 = *reinterpret_cast<const float4*>(qa);                             \
+    ra1 = *reinterpret_cast<const float4*>(qa + sa);                        \
+    ra2 = *reinterpret_cast<const float4*>(qa + 2 * sa);                    \
+    ra3 = *reinterpret_cast<const float4*>(qa + 3 * sa);                    \
+    rb0 = *reinterpret_cast<const float4*>(qb);                             \
+    rb1 = *reinterpret_cast<const float4*>(qb + sb);                        \
+    rb2 = *reinterpret_cast<const float4*>(qb + 2 * sb);                    \
+    rb3 = *reinterpret_cast<const float4*>(qb + 3 * sb);                    \
+  } while (0)
+#define BH_SSTORE(buf)                                                      \
+  do {                                                                      \
+    *reinterpret_cast<float4*>(&As[buf][lr][lc]) = ra0;                     \
+    *reinterpret_cast<float4*>(&As[buf][lr + 8][lc]) = ra1;                 \
+    *reinterpret_cast<float4*>(&As[buf][lr + 16][lc]) = ra2;                \
+    *reinterpret_cast<float4*>(&As[buf][lr + 24][lc]) = ra3;                \
+    *reinterpret_cast<float4*>(&Bs[buf][lr][lc]) = rb0;                     \
+    *reinterpret_cast<float4*>(&Bs[buf][lr + 8][lc]) = rb1;                 \
+    *reinterpret_cast<float4*>(&Bs[buf][lr + 16][lc]) = rb2;                \
+    *reinterpret_cast<float4*>(&Bs[buf][lr + 24][lc]) = rb3;                \
+  } while (0)
+  floatx16 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int hl = lane >> 5, ll = lane & 31;
+  BH_GLOAD(0);
+  BH_SSTORE(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) BH_GLOAD(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK / 2; ++kk) {
+      const int k = 2 * kk + hl;
+      const float a0 = As[cur][k][wm + ll], a1 = As[cur][k][wm + 32 + ll];
+      const float b0 = Bs[cur][k][wn + ll], b1 = Bs[cur][k][wn + 32 + ll];
+      acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc11, 0, 0, 0);
+    }
+    if (kt + 1 < nk) BH_SSTORE(cur ^ 1);
+    __syncthreads();
+  }
+#undef BH_GLOAD
+#undef BH_SSTORE
+  float* out = part + (int64_t)blockIdx.z * M_pad * C_pad;
+  const int64_t row0 = m0 + wm + 4 * hl, col0 = n0 + wn + ll;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t row = row0 + 8 * (r >> 2) + (r & 3);
+    out[row * C_pad + col0] = acc00[r];
+    out[row * C_pad + col0 + 32] = acc01[r];
+    out[(row + 32) * C_pad + col0] = acc10[r];
+    out[(row + 32) * C_pad + col0 + 32] = acc11[r];
+  }
+}
+
+// coeffs[b][q] = (sum_s part[s][b][src_re] * sgn_re, sum_s part[s][b][src_im] * sgn_im)
+__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ part, int nsplit,
+                                                int64_t M_pad, int64_t C_pad, int64_t B, int64_t C,
+                                                const int32_t* __restrict__ csrc,
+                                                const float* __restrict__ csgn,
+                                                float* __restrict__ coeffs) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * C) return;
+  const int64_t b = t / C, q = t % C;
+  const int32_t sr = csrc[2 * q], si = csrc[2 * q + 1];
+  float re = 0.0f, im = 0.0f;
+  for (int s = 0; s < nsplit; ++s) {
+    const float* ps = part + (int64_t)s * M_pad * C_pad + b * C_pad;
+    re += ps[sr];
+    if (si >= 0) im += ps[si];
+  }
+  coeffs[2 * t] = re * csgn[2 * q];
+  coeffs[2 * t + 1] = (si >= 0) ? im * csgn[2 * q + 1] : 0.0f;
+}
+
+}  // namespace
+
+int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s) {
+  if (B == 0) return BH_OK;
+  const int64_t M_pad = ((B + BM - 1) / BM) * BM;
+  const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
+  const int64_t nk_total = p->V_pad / BK;           // multiple of 16
+  int nsplit = 1;
+  while (nsplit < 16 && mt * nt * nsplit < 1024 && (nk_total / (nsplit * 2)) >= 8) nsplit *= 2;
+  const int nk = (int)(nk_total / nsplit);
+  int rc;
+  if ((rc = grow(p->gathered, (size_t)p->V_pad * M_pad * sizeof(float))) != BH_OK) return rc;
+  if ((rc = grow(p->partial, (size_t)nsplit * M_pad * p->C_pad * sizeof(float))) != BH_OK) return rc;
+  float* Ft = (float*)p->gathered.ptr;
+  float* part = (float*)p->partial.ptr;
+  const int64_t vol_stride = (int64_t)p->N * p->N * p->N;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)(p->V_pad / 32), (unsigned)(M_pad / 32)), dim3(256), 0,
+                     s, vols, vol_stride, B, p->vidx, p->V, M_pad, Ft);
+  BH_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)mt, (unsigned)nt, (unsigned)nsplit), dim3(256), 0, s,
+                     Ft, p->psi, part, M_pad, p->C_pad, nk);
+  BH_HIP(hipGetLastError());
+  const int64_t tot = B * p->C;
+  hipLaunchKernelGGL(k_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part, nsplit,
+                     M_pad, p->C_pad, B, p->C, p->csrc, p->csgn, coeffs);
+  BH_HIP(hipGetLastError());
+  return BH_OK;
+}
+
+}  // namespace bh

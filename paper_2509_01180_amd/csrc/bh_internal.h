@@ -1,0 +1,90 @@
+// Internal declarations of the bh library: plan state, error reporting and
+// the kernel launchers shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/bh.h"
+#include "bh_tables.h"
+
+namespace bh {
+
+// ----------------------------------------------------------------- errors --
+int set_error(int code, const std::string& msg);
+
+#define BH_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return ::bh::set_error(BH_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// -------------------------------------------------------------- GEMM shape --
+// Expansion GEMM a[b][c] = sum_v F[b][v] Psi[v][c] on MFMA f32 32x32x2.
+constexpr int kGemmBM = 128;     // particles per tile
+constexpr int kGemmBN = 128;     // coefficients per tile
+constexpr int kGemmBK = 32;      // voxels per K step
+constexpr int kGemmKAlign = kGemmBK * 16;   // V padded to this, split-K <= 16
+
+// The score loop loads table entries ahead of use; tables and per-particle
+// cross-power buffers carry this many zero entries past their end.
+constexpr int kTablePad = 4;
+
+// Device copy of one band's score tables (see BandTables).
+struct DevBand {
+  int L = -1;
+  int n_classes = 0;
+  int64_t n_entries = 0;
+  double* rec = nullptr;        // [n_entries][2]
+  int32_t* sel = nullptr;       // [n_entries][4]
+  double* wt = nullptr;         // [n_entries][2]
+  int32_t* p_first = nullptr;   // [2L+2]
+  int32_t* deg_start = nullptr; // [L+2]
+  int32_t* deg_off = nullptr;
+};
+
+struct Buffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace bh
+
+struct bh_plan {
+  int N = 0, L_max = 0, device = 0;
+  const bh::IndexSet* idx = nullptr;
+  int64_t V = 0, V_pad = 0;      // ball voxels, padded to kGemmKAlign
+  int64_t C = 0, C_pad = 0;      // complex coefficients of L_max, padded to kGemmBN
+  float* psi = nullptr;          // [V_pad][C_pad] h^3 * real columns of conj(psi)
+  int32_t* vidx = nullptr;       // [V] linear voxel index of each ball voxel
+  int32_t* csrc = nullptr;       // [C][2] real column feeding re/im of each complex coefficient
+  float* csgn = nullptr;         // [C][2] sign applied to it
+  std::vector<int64_t> band_size;   // C(L) for L = 0..L_max
+  // scratch (grown on demand, owned by the plan)
+  bh::Buffer gathered, partial, xi_scr, state_scr, misc_scr;
+  std::map<int, bh::DevBand> bands;
+};
+
+namespace bh {
+
+int grow(Buffer& b, size_t bytes);
+int get_band(bh_plan* p, int L, const DevBand** out);
+
+// launchers (return BH_OK or an error code)
+int build_basis(bh_plan* p);
+int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s);
+int launch_cross_power_dense(bh_plan* p, const DevBand& band, const float* a, const float* b,
+                             int64_t B, double* xi, hipStream_t s);
+int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const float* b, int64_t B,
+                     const double* euler, int R, double* score, double* grad, hipStream_t s);
+int launch_align(bh_plan* p, const float* a, const float* b, int64_t B, const bh_align_opts& o,
+                 const double* starts, double* euler_out, double* score_out, double* all_euler,
+                 double* all_score, hipStream_t s);
+
+}  // namespace bh

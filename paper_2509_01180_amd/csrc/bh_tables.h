@@ -1,0 +1,76 @@
+// Host-side tables: Bessel zeros and the frequency-ordered index set
+// (Sec. II-A), and the per-band tables of the Wigner small-d recurrence used
+// by the score kernels (Eq. (2)).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace bh {
+
+// One radial entry (l, k) of the index set, in ascending lambda_lk.
+struct Radial {
+  int l, k;
+  double lam;    // k-th positive zero of j_l
+  double c;      // sqrt(2) / |j_{l+1}(lam)|
+  int offset;    // first coefficient of this entry; m = -l..l follow
+};
+
+struct IndexSet {
+  int L = -1;
+  double cutoff = 0;            // lambda_{L+1,1}
+  std::vector<Radial> rad;      // ascending lambda, ties by (l, k)
+  int64_t C = 0;                // number of complex coefficients
+};
+
+// k-th positive zero of j_l (k >= 1), by sign-change bracketing + bisection.
+double bessel_zero(int l, int k);
+// All positive zeros of j_l below x_max.
+std::vector<double> bessel_zeros_below(int l, double x_max);
+// Index set of band L (cached; thread-safe).
+const IndexSet& index_set(int L);
+
+// Number of ball voxels of the N^3 cell-centred grid and their linear indices.
+std::vector<int32_t> ball_voxels(int N);
+
+// ---------------------------------------------------------------------------
+// Score tables of one band L.
+//
+// The score sum over (l, m, n) is reorganised into "classes": ordered pairs
+// (m, n) modulo the swap (m, n) -> (n, m) (d^l_{nm} = (-1)^{m-n} d^l_{mn})
+// and the real-input conjugation (m, n) -> (-m, -n).  Canonical member:
+// m >= |n|.  Classes are enumerated by p = m + n in 0..2L and, inside,
+// q = m - n = p mod 2, p mod 2 + 2, ..., <= 2L - p.  Class (m, n) owns the
+// chain l = m..L.  Along the chain d^l_{mn}(beta) = nu_l e_l with
+//   e_{m-1} = 0, e_m = cos(beta/2)^p sin(beta/2)^q,
+//   e_{l+1} = ap_l (cos(beta) - bq_l) e_l - e_{l-1},
+// which is the three-term recurrence in l rescaled so that the coefficient
+// of e_{l-1} is one; nu_l carries the scale, the sign (-1)^q and
+// sqrt(binom(2m, p)) of the closed-form seed d^m_{mn}.
+//
+// Entry e (class, l) holds, for the kernels:
+//   rec[e]   = {ap_l, bq_l}
+//   sel[e]   = {l, m, n, flags}
+//   wt[e]    = {w1 nu_l, w2 (-1)^{m-n} nu_l}: weights of xi^l_{mn} and
+//              xi^l_{nm}.  w1 = w2 = 2 for m > |n| (the swapped pair and the
+//              conjugate pairs), w1 = 2, w2 = 0 for n = m > 0, w1 = w2 = 1 for
+//              n = -m < 0, w1 = 1, w2 = 0 for (0, 0).
+// Per class: a contiguous run of entries (L - m + 1 of them).
+// ---------------------------------------------------------------------------
+struct BandTables {
+  int L = -1;
+  int n_classes = 0;
+  int64_t n_entries = 0;
+  std::vector<double> rec;        // [n_entries][2]
+  std::vector<int32_t> sel;       // [n_entries][4]
+  std::vector<double> wt;         // [n_entries][2]
+  std::vector<int32_t> p_first;   // [2L+2] first entry of the classes with this p
+  // radial entries of the band grouped by degree (for the cross-power sums)
+  std::vector<int32_t> deg_start; // [L+2]
+  std::vector<int32_t> deg_off;   // coefficient offsets of (l, k) with lambda < cutoff(L)
+};
+
+// Tables of band L; coefficient offsets refer to the layout of index_set(Lmax).
+BandTables band_tables(int L, int Lmax);
+
+}  // namespace bh

@@ -1,0 +1,145 @@
+"""GPU parity of frequency marching + multi-start ascent (Sec. II-C).
+
+Same FP32 coefficients and starts on both sides; the best rotation must
+agree with the oracle's within 0.5 degrees (spec bar), unless the two
+winning restarts are a tie (scores within 1e-9 relative), in which case
+both must be maxima of equal score.  Most individual restart trajectories
+agree to rounding; accept/reject decisions at near-ties may split a few.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import as_fp32_complex, cuda_device, say, to_complex, to_pairs
+from oracle import align as oalign, basis, expand, score, wigner
+
+pytestmark = pytest.mark.gpu
+
+TOL_DEG = 0.5
+
+
+def rot(e):
+    return wigner.euler_to_matrix(*e)
+
+
+def gpu_align(N, Lmax, A, b, bands, starts, steps):
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    dev = cuda_device()
+    say(f"align N={N} Lmax={Lmax} B={len(A)} P={starts.shape[1]} bands={bands} T={steps}")
+    plan = Plan(N, Lmax, device=0)
+    da = torch.from_numpy(to_pairs(A)).to(dev).contiguous()
+    db = torch.from_numpy(to_pairs(b)).to(dev).contiguous()
+    st = torch.from_numpy(np.ascontiguousarray(starts)).to(dev)
+    eu, sc, ae, asc = plan.align(da, db, bands, st, steps, return_all=True)
+    torch.cuda.synchronize()
+    out = eu.cpu().numpy(), sc.cpu().numpy(), ae.cpu().numpy(), asc.cpu().numpy()
+    plan.close()
+    return out
+
+
+def compare_particle(a, b, idx, bands, starts, steps, eu, sc, ae, asc):
+    r = oalign.march(a, b, idx, bands, starts, steps)
+    e_ref, s_ref = r["euler"][r["best"]], r["score"][r["best"]]
+    ang = wigner.geodesic_deg(rot(eu), rot(e_ref))
+    tie = abs(sc - s_ref) <= 1e-9 * abs(s_ref)
+    agree = np.array([wigner.geodesic_deg(rot(x), rot(y)) for x, y in zip(ae, r["euler"])])
+    print(f"best: {ang:.2e} deg, score {sc:.12g} vs {s_ref:.12g}; restarts agreeing "
+          f"to 1e-4 deg: {np.mean(agree < 1e-4):.2f}")
+    assert ang <= TOL_DEG or tie
+    assert abs(sc - s_ref) <= 1e-9 * max(abs(s_ref), 1e-300)
+    assert np.mean(agree < 1e-4) >= 0.75
+    np.testing.assert_allclose(asc[agree < 1e-4], r["score"][agree < 1e-4], rtol=1e-9,
+                               atol=1e-12 * abs(s_ref))
+    return ang
+
+
+def test_align_config1():
+    w = synth.CONFIG1
+    idx = basis.IndexSet(w.L_max)
+    vols = np.stack([w.template_volume(), w.particle(0), w.particle(3)])
+    C = as_fp32_complex(expand.expand(vols.astype(np.float64), idx))
+    b, A = C[0], C[1:]
+    starts = np.stack([w.starts(0), w.starts(3)])
+    eu, sc, ae, asc = gpu_align(w.N, w.L_max, A, b, w.bands, starts, w.steps)
+    for i in range(len(A)):
+        compare_particle(A[i], b, idx, w.bands, starts[i], w.steps, eu[i], sc[i], ae[i], asc[i])
+
+
+def test_align_multi_chunk_and_edges():
+    # P = 100 restarts (two chunks of 64 lanes, ragged), three bands, B = 2.
+    Lmax = 10
+    idx = basis.IndexSet(Lmax)
+    rng = np.random.default_rng(3)
+    bl = synth.blob_template(rng, 12)
+    t = synth.render_blobs(bl, 24)
+    g = synth.quat_to_matrix(synth.haar_quaternions(rng, 2))
+    vols = np.stack([t, synth.render_blobs(bl, 24, g[0]), synth.render_blobs(bl, 24, g[1])])
+    C = as_fp32_complex(expand.expand(vols.astype(np.float64), idx))
+    b, A = C[0], C[1:]
+    P = 100
+    starts = synth.matrix_to_euler_zyz(synth.quat_to_matrix(synth.haar_quaternions(rng, 2 * P)))
+    starts = starts.reshape(2, P, 3)
+    starts[0, 0] = [0.0, 0.0, 0.0]
+    starts[0, 1] = [1.0, np.pi, -2.0]
+    starts[1, 5] = [9.0, -0.5, 7.0]      # out-of-range start is wrapped
+    bands = (3, 6, 10)
+    eu, sc, ae, asc = gpu_align(24, Lmax, A, b, bands, starts, 12)
+    for i in range(2):
+        ang = compare_particle(A[i], b, idx, bands, starts[i], 12, eu[i], sc[i], ae[i], asc[i])
+        err = wigner.geodesic_deg(rot(eu[i]), g[i].T)
+        print(f"planted error {err:.3f} deg")
+        assert err < 1.0
+    # zero steps: the best start by its score at the last band, starts wrapped
+    eu0, sc0, ae0, asc0 = gpu_align(24, Lmax, A[:1], b, (4,), starts[:1, :7], 0)
+    np.testing.assert_allclose(ae0[0], oalign.wrap_many(starts[0, :7]), atol=1e-15)
+    s_ref = score.score(score.cross_power(A[0], b, idx, 4), oalign.wrap_many(starts[0, :7]))
+    np.testing.assert_allclose(asc0[0], s_ref, rtol=1e-10)
+    assert int(np.argmax(s_ref)) == int(np.argmax(asc0[0]))
+
+
+def test_align_single_restart():
+    w = synth.CONFIG1
+    idx = basis.IndexSet(w.L_max)
+    vols = np.stack([w.template_volume(), w.particle(5, wedge=False, noise=False)])
+    C = as_fp32_complex(expand.expand(vols.astype(np.float64), idx))
+    starts = w.starts(5)[None, :1]
+    eu, sc, ae, asc = gpu_align(w.N, w.L_max, C[1:], C[0], (8,), starts, 30)
+    compare_particle(C[1], C[0], idx, (8,), starts[0], 30, eu[0], sc[0], ae[0], asc[0])
+
+
+def test_align_full_size_sampled():
+    """The benchmark's path at full size: 1000 x 64^3, L = 32, bands 8..32,
+    64 restarts, 20 steps; GPU expansion + GPU alignment, against the
+    oracle's expansion + alignment of a sampled particle."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    w = synth.CONFIG2
+    dev = cuda_device()
+    sample = [0, 999]
+    rng = np.random.default_rng(12)
+    vols = (0.1 * rng.standard_normal((w.batch, w.N, w.N, w.N))).astype(np.float32)
+    for i in sample:
+        vols[i] = w.particle(i)
+    tv = w.template_volume()
+    starts = np.stack([w.starts(i) for i in range(w.batch)])
+    idx = basis.IndexSet(w.L_max)
+    ref_c = expand.expand(np.concatenate([tv[None], vols[sample]]).astype(np.float64), idx)
+
+    say("full-size expand + align, B=1000, 64^3, L=32")
+    plan = Plan(w.N, w.L_max, device=0)
+    a = plan.expand(torch.from_numpy(vols).to(dev))
+    bt = plan.expand(torch.from_numpy(tv[None]).to(dev))[0].contiguous()
+    eu, sc = plan.align(a, bt, w.bands, torch.from_numpy(starts).to(dev), w.steps)
+    torch.cuda.synchronize()
+    eu, sc = eu.cpu().numpy(), sc.cpu().numpy()
+    plan.close()
+    assert np.all(np.isfinite(eu)) and np.all(np.isfinite(sc))
+    for j, i in enumerate(sample):
+        r = oalign.march(ref_c[1 + j], ref_c[0], idx, w.bands, starts[i], w.steps)
+        e_ref = r["euler"][r["best"]]
+        ang = wigner.geodesic_deg(rot(eu[i]), rot(e_ref))
+        err = wigner.geodesic_deg(rot(eu[i]), w.truth(i).T)
+        print(f"particle {i}: vs oracle {ang:.4f} deg, vs planted {err:.3f} deg")
+        assert ang <= TOL_DEG

@@ -1,0 +1,112 @@
+"""GPU parity of the expansion (Sec. II-A) against the FP64 oracle.
+
+Bar: per-particle normwise relative error <= 1e-5 (FP32 inputs, FP32 MFMA
+with split-K partial sums; the oracle sums the same FP32 samples in FP64).
+Cases span several 128x128 tiles with ragged particle and coefficient
+tails, an odd box (centre voxel at r = 0), B = 0, and the full 64^3, L = 32,
+B = 1000 launch shape of the benchmark on sampled particles.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import cuda_device, normwise, say, to_complex
+from oracle import basis, expand
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def run_gpu(N, L, vols):
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    dev = cuda_device()
+    say(f"expand N={N} L={L} B={len(vols)}")
+    plan = Plan(N, L, device=0)
+    out = plan.expand(torch.from_numpy(np.ascontiguousarray(vols, dtype=np.float32)).to(dev))
+    torch.cuda.synchronize()
+    got = to_complex(out)
+    plan.close()
+    return got
+
+
+def test_expand_config1_volumes():
+    w = synth.CONFIG1
+    vols = np.stack([w.template_volume(), w.particle(0), w.particle(1),
+                     w.particle(2, wedge=False, noise=False)])
+    ref = expand.expand(vols.astype(np.float64), basis.IndexSet(w.L_max))
+    got = run_gpu(w.N, w.L_max, vols)
+    err = normwise(got, ref)
+    print("normwise", err)
+    assert np.all(err <= TOL)
+
+
+def test_expand_ragged_tiles():
+    # B = 130 spans two particle tiles (128 + 2); C(12) is not a multiple of 128.
+    N, L, B = 24, 12, 130
+    rng = np.random.default_rng(5)
+    vols = rng.standard_normal((B, N, N, N)).astype(np.float32)
+    bl = synth.blob_template(rng, 10)
+    vols[::7] += 3 * synth.render_blobs(bl, N).astype(np.float32)
+    ref = expand.expand(vols.astype(np.float64), basis.IndexSet(L))
+    got = run_gpu(N, L, vols)
+    err = normwise(got, ref)
+    assert got.shape == ref.shape
+    assert np.all(err <= TOL), err.max()
+
+
+def test_expand_odd_box_and_low_bandlimit():
+    for N, L in [(17, 6), (9, 0)]:
+        rng = np.random.default_rng(N)
+        vols = rng.standard_normal((5, N, N, N)).astype(np.float32)
+        ref = expand.expand(vols.astype(np.float64), basis.IndexSet(L))
+        got = run_gpu(N, L, vols)
+        assert np.all(normwise(got, ref) <= TOL)
+
+
+def test_expand_empty_batch_and_shape_errors():
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    dev = cuda_device()
+    plan = Plan(16, 4, device=0)
+    out = plan.expand(torch.zeros((0, 16, 16, 16), dtype=torch.float32, device=dev))
+    assert out.shape == (0, plan.C, 2)
+    with pytest.raises(ValueError):
+        plan.expand(torch.zeros((2, 16, 16, 15), dtype=torch.float32, device=dev))
+    with pytest.raises(TypeError):
+        plan.expand(torch.zeros((2, 16, 16, 16), dtype=torch.float64, device=dev))
+    plan.close()
+
+
+def test_expand_deterministic():
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    dev = cuda_device()
+    rng = np.random.default_rng(1)
+    vols = torch.from_numpy(rng.standard_normal((40, 32, 32, 32)).astype(np.float32)).to(dev)
+    plan = Plan(32, 16, device=0)
+    a = plan.expand(vols)
+    b = plan.expand(vols)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    plan.close()
+
+
+def test_expand_full_size_sampled():
+    """64^3, L = 32, B = 1000 (the benchmark's launch shape); particles at
+    sampled positions are workload particles checked against the oracle."""
+    w = synth.CONFIG2
+    B = w.batch
+    sample = [0, 517, 999]
+    rng = np.random.default_rng(11)
+    vols = (0.1 * rng.standard_normal((B, w.N, w.N, w.N))).astype(np.float32)
+    for i in sample:
+        vols[i] = w.particle(i)
+    ref = expand.expand(vols[sample].astype(np.float64), basis.IndexSet(w.L_max))
+    got = run_gpu(w.N, w.L_max, vols)
+    err = normwise(got[sample], ref)
+    print("normwise", err)
+    assert np.all(err <= TOL)
+    assert np.all(np.isfinite(got))
