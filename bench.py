@@ -1,0 +1,269 @@
+#!/usr/bin/env python
+"""Throughput of the ball-harmonic alignment hot path on one MI355X.
+
+Workload: 1000 subtomograms of 64^3 FP32 voxels against one 50-blob
+template (its coefficients resident, computed before timing), each particle
+with its own Haar rotation, +/-60 degree missing wedge and SNR 0.05 noise
+(synthetic stand-in for the paper's SHREC 2020 tomograms).  One step is the
+whole path over the batch: expansion to bandlimit 32 (MFMA GEMM), then
+frequency marching over bands 8, 16, 24, 32 with 20 gradient-ascent steps per
+band from 64 starting rotations per particle, and selection of the best
+restart.  Inputs are resident in HBM before the timed region.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+
+Prints one JSON line.  The roofline object describes the dominant kernel
+(the ascent kernel, summed over its per-band launches), timed with HIP
+events on the stream it runs on.  The cpu_baseline object times the FP64
+oracle on a bounded sample of the same workload on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import resource
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+PEAK_FP64_VECTOR = 78.6e12     # MI355X dense FP64 vector, FLOP/s (FMA = 2)
+PEAK_FP32_MFMA = 157.3e12      # MI355X dense FP32 matrix, FLOP/s
+PEAK_HBM = 8.0e12              # bytes/s
+
+# Operation counts of the score/gradient evaluation:
+# per (class, l) entry of the recurrence: 8 FMA accumulations + 5 recurrence
+# operations (u, ap*sin(beta), two FMA for e, two for de/dbeta) = 25 flops;
+# per class: seeds, the two phase products, the four output updates and
+# the running powers = 57 flops.
+FLOP_PER_ENTRY = 25
+FLOP_PER_CLASS = 57
+
+
+def band_counts(L: int):
+    n_entries = sum((2 * m + 1) * (L - m + 1) for m in range(L + 1))
+    n_classes = (L + 1) ** 2
+    return n_entries, n_classes
+
+
+def score_kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("bh_score.hip", "bh_eval.h"):
+        h.update(open(os.path.join(ROOT, "paper_2509_01180_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_hash: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "march_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def make_inputs(w: synth.Workload, B: int, threads: int):
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        vols = np.stack(list(ex.map(w.particle, range(B))))
+    starts = np.stack([w.starts(i) for i in range(B)])
+    return vols, starts
+
+
+def cpu_baseline(w: synth.Workload, n_particles: int):
+    """FP64 oracle (expansion + march) on the first particles of the workload."""
+    from oracle import align as oalign, basis, expand
+    idx = basis.IndexSet(w.L_max)
+    tv = w.template_volume().astype(np.float64)
+    vols = np.stack([w.particle(i) for i in range(n_particles)]).astype(np.float64)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    b = expand.expand(tv, idx)
+    A = expand.expand(vols, idx)
+    out = []
+    for i in range(n_particles):
+        r = oalign.march(A[i], b, idx, w.bands, w.starts(i), w.steps)
+        out.append(r["euler"][r["best"]])
+    dt = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    return dt, cpu, np.array(out)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=None, help="particles per step (default 1000)")
+    ap.add_argument("--cpu-sample", type=int, default=1, help="particles timed on the oracle (0: skip)")
+    ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--calib-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB before the timed "
+                         "region (reference kernel for hardware traffic counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(particles shard across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2509_01180_amd.api import Plan
+
+    w = synth.CONFIG2
+    B = args.batch or w.batch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t_gen = time.perf_counter()
+    vols_h, starts_h = make_inputs(w, B, args.threads)
+    tv = w.template_volume()
+    t_gen = time.perf_counter() - t_gen
+    print(f"# generated {B} particles in {t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    t_plan = time.perf_counter()
+    plan = Plan(w.N, w.L_max, device=0)
+    t_plan = time.perf_counter() - t_plan
+    vols = torch.from_numpy(vols_h).to(dev)
+    starts = torch.from_numpy(starts_h).to(dev)
+    b = plan.expand(torch.from_numpy(tv[None]).to(dev))[0].contiguous()   # resident template
+    a = torch.empty((B, plan.C, 2), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    print(f"# plan built in {t_plan:.2f} s", file=sys.stderr, flush=True)
+
+    def step():
+        plan.expand(vols, out=a)
+        return plan.align(a, b, w.bands, starts, w.steps)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if args.calib_mib > 0:
+        src = torch.ones(args.calib_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        eu, sc = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.profile(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = B / (ms_per_step / 1e3)
+
+    # per-kernel event timing over the timed region
+    kern = {}
+    for name in ("gather", "gemm", "reduce", "xi_classes", "band_weight", "march_L*", "select"):
+        n, ms, work = plan.profile_read(name)
+        kern[name.rstrip("*")] = {"launches": n, "ms_per_step": ms / max(args.steps, 1)}
+    n_m, ms_m, _ = plan.profile_read("march_L*")
+    flops_march = 0
+    for L in w.bands:
+        ne, nc = band_counts(L)
+        flops_march += B * w.restarts * (w.steps + 1) * (FLOP_PER_ENTRY * ne + FLOP_PER_CLASS * nc)
+    launches_per_step = n_m / args.steps
+    flops_per_launch = flops_march / launches_per_step
+    avg_launch_s = (ms_m / n_m) / 1e3
+    achieved = flops_per_launch / avg_launch_s
+    traffic = load_traffic(score_kernel_sources_hash())
+
+    n_g, ms_g, _ = plan.profile_read("gemm")
+    from paper_2509_01180_amd.api import ball_voxels
+    V = ball_voxels(w.N)
+    gemm_flops = 2.0 * B * V * plan.C
+    gemm_achieved = gemm_flops / ((ms_g / n_g) / 1e3)
+
+    # accuracy against the planted rotations (context; the wedge and noise set it)
+    eu_h = eu.cpu().numpy()
+    R_est = synth.euler_zyz_to_matrix(eu_h)
+    R_true = np.stack([synth.quat_to_matrix(synth.haar_quaternions(synth.seed_rng(w.config, 1, i, 1), 1))[0]
+                       for i in range(B)])
+    d = np.linalg.norm(R_est - np.transpose(R_true, (0, 2, 1)), axis=(1, 2))
+    ang = np.degrees(2 * np.arcsin(np.minimum(1.0, d / (2 * np.sqrt(2)))))
+
+    result = {
+        "metric": "subtomograms aligned/s (64^3, L=32)",
+        "value": round(value, 2),
+        "unit": "subtomograms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32/f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"plain path: {B} x 64^3 fp32 subtomograms vs one 50-blob template, "
+                        "L=32, bands 8-16-24-32, 20 ascent steps/band, 64 restarts, "
+                        "+/-60 deg wedge, SNR 0.05",
+            "global_batch": B, "box": w.N, "L_max": w.L_max, "bands": list(w.bands),
+            "steps_per_band": w.steps, "restarts": w.restarts,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "kernel": "k_march (score+gradient+ascent, all band launches)",
+            "bound": "alu",
+            "achieved": round(achieved / 1e12, 3),
+            "peak": PEAK_FP64_VECTOR / 1e12,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP64_VECTOR, 4),
+            "traffic": traffic,
+            "flops_per_launch": flops_per_launch,
+            "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+        },
+        "roofline_expand": {
+            "kernel": "k_gemm_f32", "bound": "mfma",
+            "achieved": round(gemm_achieved / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12,
+            "unit": "TFLOP/s", "frac": round(gemm_achieved / PEAK_FP32_MFMA, 4),
+            "avg_launch_ms": round(ms_g / n_g, 4),
+        },
+        "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in kern.items()},
+        "accuracy": {"median_deg_vs_planted": round(float(np.median(ang)), 3),
+                     "p90_deg_vs_planted": round(float(np.percentile(ang, 90)), 3)},
+        "setup": {"input_generation_s": round(t_gen, 1), "plan_build_s": round(t_plan, 2)},
+    }
+
+    if args.cpu_sample > 0:
+        dt, cpu, e_oracle = cpu_baseline(w, args.cpu_sample)
+        Ro = synth.euler_zyz_to_matrix(e_oracle)
+        dd = np.linalg.norm(Ro - R_est[:args.cpu_sample], axis=(1, 2))
+        ang_o = np.degrees(2 * np.arcsin(np.minimum(1.0, dd / (2 * np.sqrt(2)))))
+        result["cpu_baseline"] = {
+            "value": round(args.cpu_sample / dt, 5),
+            "unit": "subtomograms/s",
+            "cores": max(1, int(round(cpu / dt))),
+            "kind": "oracle",
+            "sample": f"first {args.cpu_sample} particle(s) of the workload: FP64 oracle expansion "
+                      f"(64^3, L=32) + 64-restart march, bands 8-16-24-32, 20 steps; "
+                      f"{dt:.1f} s wall, {cpu:.1f} s CPU on {os.cpu_count()} visible cores",
+        }
+        result["accuracy"]["max_deg_vs_oracle_on_sample"] = round(float(ang_o.max()), 4)
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

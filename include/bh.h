@@ -169,6 +169,23 @@ int bh_align(bh_plan* p, const float* a, const float* b, int64_t B,
              double* euler_out, double* score_out,
              double* all_euler, double* all_score, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Per-kernel timing (for measurement; off by default).
+ * bh_profile_enable(p, 1) synchronises the device, clears earlier records
+ * and starts recording a pair of HIP events on the call's stream around
+ * every kernel launch of this plan; bh_profile_enable(p, 0) stops.
+ * bh_profile_read waits for the recorded events whose kernel name equals
+ * `name` (or starts with it when `name` ends in '*') and returns their
+ * number, summed duration in milliseconds and summed work units (kernel
+ * specific: particles x evaluations x class entries for the score kernels,
+ * particles for the expansion).  Kernel names: "gather", "gemm", "reduce",
+ * "xi_classes", "band_weight", "march_L<L>", "select", "correlate_L<L>",
+ * "xi_dense".  Outputs may be NULL.
+ * ------------------------------------------------------------------- */
+int bh_profile_enable(bh_plan* p, int enable);
+int bh_profile_read(bh_plan* p, const char* name, int64_t* launches, double* total_ms,
+                    int64_t* work);
+
 #ifdef __cplusplus
 }
 #endif

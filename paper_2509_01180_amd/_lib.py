@@ -57,6 +57,9 @@ SIGNATURES = {
     "bh_cross_power": (_I, [_P, _P, _P, _I64, _I, _P, _P]),
     "bh_correlate": (_I, [_P, _P, _P, _I64, _I, _P, _I, _P, _P, _P]),
     "bh_align": (_I, [_P, _P, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),
+    "bh_profile_enable": (_I, [_P, _I]),
+    "bh_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(_I64)]),
 }
 
 _lib = None

@@ -110,6 +110,21 @@ class Plan:
     def num_coeffs(self, L: int) -> int:
         return check(lib().bh_plan_num_coeffs(self._h, int(L)), "bh_plan_num_coeffs")
 
+    # ------------------------------------------------------- profiling --
+    def profile(self, enable: bool = True) -> None:
+        """Start (clearing earlier records) or stop per-kernel event timing."""
+        check(lib().bh_profile_enable(self._h, 1 if enable else 0), "bh_profile_enable")
+
+    def profile_read(self, name: str):
+        """(launches, total_ms, work_units) of the recorded kernels named `name`
+        (a trailing '*' matches a prefix)."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        w = ctypes.c_int64()
+        check(lib().bh_profile_read(self._h, name.encode(), ctypes.byref(n), ctypes.byref(ms),
+                                    ctypes.byref(w)), "bh_profile_read")
+        return n.value, ms.value, w.value
+
     # ----------------------------------------------------------- calls --
     def expand(self, vols: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """vols [B, N, N, N] float32 -> coefficients [B, C(L_max), 2] float32."""

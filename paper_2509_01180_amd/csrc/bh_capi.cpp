@@ -66,6 +66,46 @@ int set_error(int code, const std::string& msg) {
   return code;
 }
 
+hipEvent_t Profiler::take() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Profiler::clear() {
+  for (auto& r : recs) {
+    pool.push_back(r.start);
+    pool.push_back(r.stop);
+  }
+  recs.clear();
+}
+
+void Profiler::destroy() {
+  clear();
+  for (hipEvent_t e : pool)
+    if (e) (void)hipEventDestroy(e);
+  pool.clear();
+}
+
+ProfScope::ProfScope(bh_plan* p, const std::string& name, hipStream_t s, int64_t work)
+    : p_(p), s_(s) {
+  if (!p_->prof.on) return;
+  hipEvent_t a = p_->prof.take(), b = p_->prof.take();
+  if (!a || !b) return;
+  if (hipEventRecord(a, s_) != hipSuccess) return;
+  p_->prof.recs.push_back({name, a, b, work});
+  idx_ = (int)p_->prof.recs.size() - 1;
+}
+
+ProfScope::~ProfScope() {
+  if (idx_ >= 0) (void)hipEventRecord(p_->prof.recs[idx_].stop, s_);
+}
+
 int grow(Buffer& b, size_t bytes) {
   if (bytes <= b.bytes) return BH_OK;
   if (b.ptr) {
@@ -213,7 +253,48 @@ void bh_plan_destroy(bh_plan* p) {
   for (Buffer* b : {&p->gathered, &p->partial, &p->xi_scr, &p->state_scr, &p->misc_scr})
     if (b->ptr) (void)hipFree(b->ptr);
   for (auto& kv : p->bands) free_band(kv.second);
+  p->prof.destroy();
   delete p;
+}
+
+int bh_profile_enable(bh_plan* p, int enable) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (enable) {
+      BH_HIP(hipDeviceSynchronize());
+      p->prof.clear();
+    }
+    p->prof.on = enable != 0;
+    return BH_OK;
+  });
+}
+
+int bh_profile_read(bh_plan* p, const char* name, int64_t* launches, double* total_ms,
+                    int64_t* work) {
+  if (!p || !name) return set_error(BH_EINVAL, "NULL argument");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    std::string pat(name);
+    bool prefix = !pat.empty() && pat.back() == '*';
+    if (prefix) pat.pop_back();
+    int64_t n = 0, w = 0;
+    double ms = 0.0;
+    for (auto& r : p->prof.recs) {
+      const bool hit = prefix ? r.name.compare(0, pat.size(), pat) == 0 : r.name == pat;
+      if (!hit) continue;
+      BH_HIP(hipEventSynchronize(r.stop));
+      float t = 0.0f;
+      BH_HIP(hipEventElapsedTime(&t, r.start, r.stop));
+      ms += t;
+      n += 1;
+      w += r.work;
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
+    if (work) *work = w;
+    return BH_OK;
+  });
 }
 
 int64_t bh_plan_num_coeffs(const bh_plan* p, int L) {

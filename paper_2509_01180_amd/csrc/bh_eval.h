@@ -50,25 +50,47 @@ struct Acc {
   double S, ga, gb, gg;
 };
 
+// One step of the rescaled recurrence for chain entry x/c (see below).
+#define BH_CHAIN_STEP(X4, C2, EA, RA, EB, RB)                                 \
+  do {                                                                        \
+    t1r = fma((X4).x, EA, t1r);                                               \
+    t1i = fma((X4).y, EA, t1i);                                               \
+    t2r = fma((X4).z, EA, t2r);                                               \
+    t2i = fma((X4).w, EA, t2i);                                               \
+    r1r = fma((X4).x, RA, r1r);                                               \
+    r1i = fma((X4).y, RA, r1i);                                               \
+    r2r = fma((X4).z, RA, r2r);                                               \
+    r2i = fma((X4).w, RA, r2i);                                               \
+    const double u_ = (C2).x * (A.x - (C2).y);                                \
+    const double msa_ = (C2).x * msb;                                         \
+    EB = fma(u_, EA, -EB);                                                    \
+    RB = fma(msa_, EA, fma(u_, RA, -RB));                                     \
+  } while (0)
+
 // Partial sums of one wave over its classes p = wave, wave + W, ...
+//
+// Chain loop: four entries per round.  The four X and rec entries of a
+// round are wave-uniform and fetched together with scalar loads (one wait
+// per round: scalar loads return out of order, so a wait drains them all);
+// (ea, ra) and (eb, rb) hold e, de/dbeta of two consecutive degrees and each
+// step overwrites the older pair, so no register moves are needed.
 BH_HD inline Acc eval_wave(const Angles& A, int wave, int W, int L,
-                                const int32_t* __restrict__ p_first,
-                                const double* __restrict__ rec, const double* __restrict__ X) {
+                           const int32_t* __restrict__ p_first,
+                           const double* __restrict__ rec, const double* __restrict__ X) {
   Acc acc = {0.0, 0.0, 0.0, 0.0};
-  // c^p, c^{max(p-1,0)}, c^{p+1} for the first p of this wave, and c^W, c^{W-1}
-  double cW = 1.0, cW1 = 1.0;
-  for (int i = 0; i < W; ++i) cW *= A.c;
-  for (int i = 0; i < W - 1; ++i) cW1 *= A.c;
-  double cp = 1.0;
-  for (int i = 0; i < wave; ++i) cp *= A.c;
-  double cpm1 = 1.0;
-  for (int i = 0; i < wave - 1; ++i) cpm1 *= A.c;
-  double cpp1 = cp * A.c;
   const double msb = -A.sb;
+  // Phi_p = e^{-i p sigma} by a running product over this wave's p values
+  double s0, c0, sw, cw;
+  sincos((double)wave * A.sigma, &s0, &c0);
+  sincos((double)W * A.sigma, &sw, &cw);
+  cplx Phi = {c0, -s0};
+  const cplx PhiW = {cw, -sw};
   for (int p = wave; p <= 2 * L; p += W) {
-    double sp, cpp;
-    sincos((double)p * A.sigma, &sp, &cpp);
-    const cplx Phi = {cpp, -sp};
+    // c^{max(p-1,0)}, c^p, c^{p+1}
+    double cpm1 = 1.0;
+    for (int i = 1; i < p; ++i) cpm1 *= A.c;
+    const double cp = (p > 0) ? cpm1 * A.c : 1.0;
+    const double cpp1 = cp * A.c;
     int off = p_first[p];
     const int q0 = p & 1;
     cplx Th = q0 ? A.th1 : cplx{1.0, 0.0};
@@ -78,59 +100,35 @@ BH_HD inline Acc eval_wave(const Angles& A, int wave, int W, int L,
       const int m = (p + q) >> 1, n = (p - q) >> 1;
       const int len = L - m + 1;
       // seeds: e_m = c^p s^q, r_m = d/dbeta e_m = (q c^{p+1} s^{q-1} - p c^{p-1} s^{q+1}) / 2
-      double e = cp * sq;
-      double r = 0.5 * ((double)q * cpp1 * sqm1 - (double)p * cpm1 * (sq * A.s));
+      double ea = cp * sq;
+      double ra = 0.5 * ((double)q * cpp1 * sqm1 - (double)p * cpm1 * (sq * A.s));
+      double eb = 0.0, rb = 0.0;
       double t1r = 0, t1i = 0, t2r = 0, t2i = 0, r1r = 0, r1i = 0, r2r = 0, r2i = 0;
-      const double* Xc = X + 4 * (int64_t)off;
-      const double* Rc = rec + 2 * (int64_t)off;
-      // Two chain entries per iteration: (ea, ra) hold e_i, r_i and (eb, rb)
-      // hold e_{i-1}, r_{i-1}; each step overwrites the older pair, so no
-      // register moves are needed.  The next pair's table entries are loaded
-      // one iteration ahead (buffers are padded past their last entry).
-      double ea = e, ra = r, eb = 0.0, rb = 0.0;
-      double4 xa = *reinterpret_cast<const double4*>(Xc);
-      double4 xb = *reinterpret_cast<const double4*>(Xc + 4);
-      double2 ca = *reinterpret_cast<const double2*>(Rc);
-      double2 cb = *reinterpret_cast<const double2*>(Rc + 2);
-      for (int i = 0; i < len; i += 2) {
-        const double4 nxa = *reinterpret_cast<const double4*>(Xc + 4 * (i + 2));
-        const double4 nxb = *reinterpret_cast<const double4*>(Xc + 4 * (i + 3));
-        const double2 nca = *reinterpret_cast<const double2*>(Rc + 2 * (i + 2));
-        const double2 ncb = *reinterpret_cast<const double2*>(Rc + 2 * (i + 3));
-        // entry i: accumulate with e_i, then e_{i+1} -> (eb, rb)
-        t1r = fma(xa.x, ea, t1r);
-        t1i = fma(xa.y, ea, t1i);
-        t2r = fma(xa.z, ea, t2r);
-        t2i = fma(xa.w, ea, t2i);
-        r1r = fma(xa.x, ra, r1r);
-        r1i = fma(xa.y, ra, r1i);
-        r2r = fma(xa.z, ra, r2r);
-        r2i = fma(xa.w, ra, r2i);
-        {
-          const double u = ca.x * (A.x - ca.y);
-          const double msa = ca.x * msb;
-          eb = fma(u, ea, -eb);
-          rb = fma(msa, ea, fma(u, ra, -rb));
-        }
-        if (i + 1 < len) {
-          // entry i+1: accumulate with e_{i+1}, then e_{i+2} -> (ea, ra)
-          t1r = fma(xb.x, eb, t1r);
-          t1i = fma(xb.y, eb, t1i);
-          t2r = fma(xb.z, eb, t2r);
-          t2i = fma(xb.w, eb, t2i);
-          r1r = fma(xb.x, rb, r1r);
-          r1i = fma(xb.y, rb, r1i);
-          r2r = fma(xb.z, rb, r2r);
-          r2i = fma(xb.w, rb, r2i);
-          const double u = cb.x * (A.x - cb.y);
-          const double msa = cb.x * msb;
-          ea = fma(u, eb, -ea);
-          ra = fma(msa, eb, fma(u, rb, -ra));
-        }
-        xa = nxa;
-        xb = nxb;
-        ca = nca;
-        cb = ncb;
+      const double4* Xc = reinterpret_cast<const double4*>(X) + off;
+      const double2* Rc = reinterpret_cast<const double2*>(rec) + off;
+      // Full rounds of four entries: straight-line code, one load batch and
+      // one wait per round.  Then a tail of two and/or one entries.
+      const int n4 = len & ~3;
+      int i = 0;
+      for (; i < n4; i += 4) {
+        const double4 x0 = Xc[i], x1 = Xc[i + 1], x2 = Xc[i + 2], x3 = Xc[i + 3];
+        const double2 c0_ = Rc[i], c1 = Rc[i + 1], c2 = Rc[i + 2], c3 = Rc[i + 3];
+        BH_CHAIN_STEP(x0, c0_, ea, ra, eb, rb);
+        BH_CHAIN_STEP(x1, c1, eb, rb, ea, ra);
+        BH_CHAIN_STEP(x2, c2, ea, ra, eb, rb);
+        BH_CHAIN_STEP(x3, c3, eb, rb, ea, ra);
+      }
+      if (len & 2) {
+        const double4 x0 = Xc[i], x1 = Xc[i + 1];
+        const double2 c0_ = Rc[i], c1 = Rc[i + 1];
+        BH_CHAIN_STEP(x0, c0_, ea, ra, eb, rb);
+        BH_CHAIN_STEP(x1, c1, eb, rb, ea, ra);
+        i += 2;
+      }
+      if (len & 1) {
+        const double4 x0 = Xc[i];
+        const double2 c0_ = Rc[i];
+        BH_CHAIN_STEP(x0, c0_, ea, ra, eb, rb);
       }
       const cplx W1 = cmul(Phi, Th);
       const cplx W2 = cmulc(Phi, Th);
@@ -145,15 +143,10 @@ BH_HD inline Acc eval_wave(const Angles& A, int wave, int W, int L,
       sqm1 = (q == 0) ? A.s : sqm1 * A.s2;
       sq *= A.s2;
     }
-    if (p == 0) {
-      cpm1 = cW1;
-    } else {
-      cpm1 *= cW;
-    }
-    cp *= cW;
-    cpp1 *= cW;
+    Phi = cmul(Phi, PhiW);
   }
   return acc;
 }
+#undef BH_CHAIN_STEP
 
 }  // namespace bh

@@ -154,15 +154,24 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
   float* Ft = (float*)p->gathered.ptr;
   float* part = (float*)p->partial.ptr;
   const int64_t vol_stride = (int64_t)p->N * p->N * p->N;
+  {
+  ProfScope ps(p, "gather", s, B);
   hipLaunchKernelGGL(k_gather, dim3((unsigned)(p->V_pad / 32), (unsigned)(M_pad / 32)), dim3(256), 0,
                      s, vols, vol_stride, B, p->vidx, p->V, M_pad, Ft);
+  }
   BH_HIP(hipGetLastError());
+  {
+  ProfScope ps(p, "gemm", s, B);
   hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)mt, (unsigned)nt, (unsigned)nsplit), dim3(256), 0, s,
                      Ft, p->psi, part, M_pad, p->C_pad, nk);
+  }
   BH_HIP(hipGetLastError());
   const int64_t tot = B * p->C;
+  {
+  ProfScope ps(p, "reduce", s, B);
   hipLaunchKernelGGL(k_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part, nsplit,
                      M_pad, p->C_pad, B, p->C, p->csrc, p->csgn, coeffs);
+  }
   BH_HIP(hipGetLastError());
   return BH_OK;
 }

@@ -54,6 +54,22 @@ struct Buffer {
   size_t bytes = 0;
 };
 
+// Opt-in per-launch timing: a pair of HIP events recorded on the launch
+// stream around each kernel while enabled.
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    std::string name;
+    hipEvent_t start, stop;
+    int64_t work;      // caller-defined work units of the launch (for reporting)
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t take();
+  void clear();
+  void destroy();
+};
+
 }  // namespace bh
 
 struct bh_plan {
@@ -69,9 +85,25 @@ struct bh_plan {
   // scratch (grown on demand, owned by the plan)
   bh::Buffer gathered, partial, xi_scr, state_scr, misc_scr;
   std::map<int, bh::DevBand> bands;
+  bh::Profiler prof;
 };
 
 namespace bh {
+
+// Records start/stop events around the launches made during its lifetime
+// (when the plan's profiler is on).
+class ProfScope {
+ public:
+  ProfScope(bh_plan* p, const std::string& name, hipStream_t s, int64_t work = 0);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  bh_plan* p_;
+  hipStream_t s_;
+  int idx_ = -1;
+};
 
 int grow(Buffer& b, size_t bytes);
 int get_band(bh_plan* p, int L, const DevBand** out);

@@ -27,6 +27,7 @@
 #include "bh_internal.h"
 
 #include <cmath>
+#include <string>
 
 namespace bh {
 namespace {
@@ -185,6 +186,12 @@ __global__ __launch_bounds__(64 * W) void k_correlate(const int32_t* __restrict_
 }
 
 // One band of the ascent for 64 restarts of one particle (see bh.h).
+//
+// Every evaluation is split over the W waves; the ascent state of the 64
+// lanes lives in LDS and is updated by wave 0 between two barriers, so the
+// other waves carry no optimiser state through the evaluation.
+enum { ST_XA, ST_XB, ST_XG, ST_S, ST_GA, ST_GB, ST_GG, ST_ETA, ST_TA, ST_TB, ST_TG, ST_N };
+
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_march(const int32_t* __restrict__ p_first,
                                                   const double* __restrict__ rec,
@@ -193,52 +200,86 @@ __global__ __launch_bounds__(64 * W) void k_march(const int32_t* __restrict__ p_
                                                   int steps, double step_init, double grow,
                                                   double shrink, double* __restrict__ state,
                                                   double* __restrict__ sscore) {
-  __shared__ double buf[2][W * 4 * 64];
+  __shared__ double red[W * 4 * 64];
+  __shared__ double st[ST_N * 64];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t pb = blockIdx.y;
   const int64_t r = (int64_t)blockIdx.x * 64 + lane;
   const bool active = r < P;
   const double* Xp = X + pb * n_entries * 4;
-  double xa = 0.0, xb = 0.0, xg = 0.0;
-  if (active) {
-    const double* st = state + (pb * P + r) * 3;
-    xa = st[0];
-    xb = st[1];
-    xg = st[2];
-  }
-  wrap_euler(xa, xb, xg);
-  const double wb = Wb[pb];
-  double eta = (wb > 0.0) ? step_init / wb : 0.0;
-  Acc cur = reduce_waves(eval_wave(prep(xa, xb, xg), wave, W, L, p_first, rec, Xp), buf[0], wave,
-                         lane, W);
-  for (int t = 0; t < steps; ++t) {
-    // natural-gradient direction at the current point
-    const double cb = cos(xb);
-    double s2 = 1.0 - cb * cb;
-    s2 = s2 > kSin2Floor ? s2 : kSin2Floor;
-    const double da = (cur.ga - cb * cur.gg) / s2;
-    const double dg = (cur.gg - cb * cur.ga) / s2;
-    double ta = xa + eta * da, tb = xb + eta * cur.gb, tg = xg + eta * dg;
-    wrap_euler(ta, tb, tg);
-    const Acc trial = reduce_waves(eval_wave(prep(ta, tb, tg), wave, W, L, p_first, rec, Xp),
-                                   buf[(t + 1) & 1], wave, lane, W);
-    if (trial.S >= cur.S) {
-      xa = ta;
-      xb = tb;
-      xg = tg;
-      cur = trial;
-      eta *= grow;
-    } else {
-      eta *= shrink;
+  if (wave == 0) {
+    double xa = 0.0, xb = 0.0, xg = 0.0;
+    if (active) {
+      const double* s0 = state + (pb * P + r) * 3;
+      xa = s0[0];
+      xb = s0[1];
+      xg = s0[2];
     }
+    wrap_euler(xa, xb, xg);
+    const double wb = Wb[pb];
+    st[ST_TA * 64 + lane] = xa;
+    st[ST_TB * 64 + lane] = xb;
+    st[ST_TG * 64 + lane] = xg;
+    st[ST_ETA * 64 + lane] = (wb > 0.0) ? step_init / wb : 0.0;
+  }
+  __syncthreads();
+  for (int t = 0; t <= steps; ++t) {
+    const Angles A = prep(st[ST_TA * 64 + lane], st[ST_TB * 64 + lane], st[ST_TG * 64 + lane]);
+    const Acc mine = eval_wave(A, wave, W, L, p_first, rec, Xp);
+    red[(wave * 4 + 0) * 64 + lane] = mine.S;
+    red[(wave * 4 + 1) * 64 + lane] = mine.ga;
+    red[(wave * 4 + 2) * 64 + lane] = mine.gb;
+    red[(wave * 4 + 3) * 64 + lane] = mine.gg;
+    __syncthreads();
+    if (wave == 0) {
+      Acc tr = {0.0, 0.0, 0.0, 0.0};
+      for (int w = 0; w < W; ++w) {
+        tr.S += red[(w * 4 + 0) * 64 + lane];
+        tr.ga += red[(w * 4 + 1) * 64 + lane];
+        tr.gb += red[(w * 4 + 2) * 64 + lane];
+        tr.gg += red[(w * 4 + 3) * 64 + lane];
+      }
+      double eta = st[ST_ETA * 64 + lane];
+      // t == 0: the carried point itself; later: accept if not worse
+      const bool take = (t == 0) || (tr.S >= st[ST_S * 64 + lane]);
+      if (take) {
+        st[ST_XA * 64 + lane] = st[ST_TA * 64 + lane];
+        st[ST_XB * 64 + lane] = st[ST_TB * 64 + lane];
+        st[ST_XG * 64 + lane] = st[ST_TG * 64 + lane];
+        st[ST_S * 64 + lane] = tr.S;
+        st[ST_GA * 64 + lane] = tr.ga;
+        st[ST_GB * 64 + lane] = tr.gb;
+        st[ST_GG * 64 + lane] = tr.gg;
+      }
+      if (t > 0) eta *= take ? grow : shrink;
+      st[ST_ETA * 64 + lane] = eta;
+      if (t < steps) {
+        // natural-gradient step from the current point
+        const double xa = st[ST_XA * 64 + lane], xb = st[ST_XB * 64 + lane],
+                     xg = st[ST_XG * 64 + lane];
+        const double ga = st[ST_GA * 64 + lane], gb = st[ST_GB * 64 + lane],
+                     gg = st[ST_GG * 64 + lane];
+        const double cb = cos(xb);
+        double s2 = 1.0 - cb * cb;
+        s2 = s2 > kSin2Floor ? s2 : kSin2Floor;
+        double ta = xa + eta * ((ga - cb * gg) / s2);
+        double tb = xb + eta * gb;
+        double tg = xg + eta * ((gg - cb * ga) / s2);
+        wrap_euler(ta, tb, tg);
+        st[ST_TA * 64 + lane] = ta;
+        st[ST_TB * 64 + lane] = tb;
+        st[ST_TG * 64 + lane] = tg;
+      }
+    }
+    __syncthreads();
   }
   if (wave == 0 && active) {
-    double* st = state + (pb * P + r) * 3;
-    st[0] = xa;
-    st[1] = xb;
-    st[2] = xg;
-    sscore[pb * P + r] = cur.S;
+    double* so = state + (pb * P + r) * 3;
+    so[0] = st[ST_XA * 64 + lane];
+    so[1] = st[ST_XB * 64 + lane];
+    so[2] = st[ST_XG * 64 + lane];
+    sscore[pb * P + r] = st[ST_S * 64 + lane];
   }
 }
 
@@ -276,25 +317,31 @@ __global__ __launch_bounds__(64) void k_select(const double* __restrict__ state,
 }
 
 int pick_waves(int64_t groups, int L) {
-  // Enough waves to fill the chip when there are few workgroups; classes
-  // are split by p = 0..2L, so more than 2L+1 waves would idle.
+  // About 4096 resident waves fill the chip (256 CUs x 4 SIMDs x 4 waves
+  // at the score kernels' register use): few workgroups get more waves
+  // each.  Classes are split by p = 0..2L, so more than 2L+1 waves idle.
   int W = 4;
-  if (groups < 1024) W = 8;
-  if (groups < 256) W = 16;
+  if (groups * 8 <= 4096) W = 8;
+  if (groups * 16 <= 4096) W = 16;
   while (W > 4 && W > 2 * L + 1) W /= 2;
   return W;
 }
 
 template <int W>
-void launch_correlate_w(dim3 grid, hipStream_t s, const DevBand& band, const double* X, int L,
-                        const double* euler, int R, double* score, double* grad) {
+void launch_correlate_w(bh_plan* p, dim3 grid, hipStream_t s, const DevBand& band, const double* X,
+                        int L, const double* euler, int R, double* score, double* grad) {
+  ProfScope ps(p, "correlate_L" + std::to_string(L), s,
+               (int64_t)grid.y * R * band.n_entries);
   hipLaunchKernelGGL(k_correlate<W>, grid, dim3(64 * W), 0, s, band.p_first, band.rec, X,
                      band.n_entries, L, euler, R, score, grad);
 }
 
 template <int W>
-void launch_march_w(dim3 grid, hipStream_t s, const DevBand& band, const double* X, int L,
-                    const double* Wb, int P, const bh_align_opts& o, double* state, double* sscore) {
+void launch_march_w(bh_plan* p, dim3 grid, hipStream_t s, const DevBand& band, const double* X,
+                    int L, const double* Wb, int P, const bh_align_opts& o, double* state,
+                    double* sscore) {
+  ProfScope ps(p, "march_L" + std::to_string(L), s,
+               (int64_t)grid.y * P * (o.steps_per_band + 1) * band.n_entries);
   hipLaunchKernelGGL(k_march<W>, grid, dim3(64 * W), 0, s, band.p_first, band.rec, X,
                      band.n_entries, L, Wb, P, o.steps_per_band, o.step_init, o.step_grow,
                      o.step_shrink, state, sscore);
@@ -306,6 +353,7 @@ int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b
   int rc = grow(p->xi_scr, ((size_t)B * band.n_entries + kTablePad) * 4 * sizeof(double));
   if (rc != BH_OK) return rc;
   *X = (double*)p->xi_scr.ptr;
+  ProfScope ps(p, "xi_classes", s, B);
   hipLaunchKernelGGL(k_xi_classes, dim3((unsigned)((band.n_entries + 127) / 128), (unsigned)B),
                      dim3(128), 0, s, a, b, p->C, band.n_entries, band.sel, band.wt,
                      band.deg_start, band.deg_off, *X);
@@ -319,6 +367,7 @@ int launch_cross_power_dense(bh_plan* p, const DevBand& band, const float* a, co
                              int64_t B, double* xi, hipStream_t s) {
   const int L = band.L;
   const int64_t E = (int64_t)(L + 1) * (4LL * (L + 1) * (L + 1) - 1) / 3;
+  ProfScope ps(p, "xi_dense", s, B);
   hipLaunchKernelGGL(k_xi_dense, dim3((unsigned)((E + 255) / 256), (unsigned)B), dim3(256), 0, s, a,
                      b, p->C, L, band.deg_start, band.deg_off, E, xi);
   BH_HIP(hipGetLastError());
@@ -333,9 +382,9 @@ int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const floa
   const int64_t chunks = (R + 63) / 64;
   const dim3 grid((unsigned)chunks, (unsigned)B);
   const int W = pick_waves(chunks * B, band.L);
-  if (W == 16) launch_correlate_w<16>(grid, s, band, X, band.L, euler, R, score, grad);
-  else if (W == 8) launch_correlate_w<8>(grid, s, band, X, band.L, euler, R, score, grad);
-  else launch_correlate_w<4>(grid, s, band, X, band.L, euler, R, score, grad);
+  if (W == 16) launch_correlate_w<16>(p, grid, s, band, X, band.L, euler, R, score, grad);
+  else if (W == 8) launch_correlate_w<8>(p, grid, s, band, X, band.L, euler, R, score, grad);
+  else launch_correlate_w<4>(p, grid, s, band, X, band.L, euler, R, score, grad);
   BH_HIP(hipGetLastError());
   return BH_OK;
 }
@@ -364,17 +413,23 @@ int launch_align(bh_plan* p, const float* a, const float* b, int64_t B, const bh
   for (const DevBand* band : bands) {
     double* X = nullptr;
     if ((rc = prepare_band(p, *band, a, b, B, &X, s)) != BH_OK) return rc;
-    hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, b, p->C, band->L,
-                       band->deg_start, band->deg_off, Wb);
+    {
+      ProfScope ps(p, "band_weight", s, B);
+      hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, b, p->C, band->L,
+                         band->deg_start, band->deg_off, Wb);
+    }
     BH_HIP(hipGetLastError());
     const int W = pick_waves(chunks * B, band->L);
-    if (W == 16) launch_march_w<16>(grid, s, *band, X, band->L, Wb, P, o, state, sscore);
-    else if (W == 8) launch_march_w<8>(grid, s, *band, X, band->L, Wb, P, o, state, sscore);
-    else launch_march_w<4>(grid, s, *band, X, band->L, Wb, P, o, state, sscore);
+    if (W == 16) launch_march_w<16>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore);
+    else if (W == 8) launch_march_w<8>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore);
+    else launch_march_w<4>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore);
     BH_HIP(hipGetLastError());
   }
+  {
+  ProfScope ps(p, "select", s, B);
   hipLaunchKernelGGL(k_select, dim3((unsigned)B), dim3(64), 0, s, state, sscore, P, euler_out,
                      score_out);
+  }
   BH_HIP(hipGetLastError());
   if (all_euler)
     BH_HIP(hipMemcpyAsync(all_euler, state, (size_t)B * P * 3 * sizeof(double),
