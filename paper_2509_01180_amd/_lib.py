@@ -11,7 +11,8 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libbh.so")
+# BH_LIBRARY selects another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("BH_LIBRARY") or os.path.join(_PKG, "libbh.so")
 
 BH_OK, BH_EINVAL, BH_ENOMEM, BH_EDEVICE, BH_EUNSUPPORTED = 0, -1, -2, -3, -4
 BH_MAX_L = 64

@@ -39,8 +39,8 @@ int guarded(F&& f) {
 }
 
 void free_band(DevBand& b) {
-  for (void* q : {(void*)b.rec, (void*)b.sel, (void*)b.wt, (void*)b.p_first, (void*)b.deg_start,
-                  (void*)b.deg_off})
+  for (void* q : {(void*)b.rec, (void*)b.sel, (void*)b.wt, (void*)b.p_first, (void*)b.wave_p,
+                  (void*)b.deg_start, (void*)b.deg_off})
     if (q) (void)hipFree(q);
   b = DevBand();
 }
@@ -140,6 +140,7 @@ int get_band(bh_plan* p, int L, const DevBand** out) {
       (rc = upload_vec(t.sel, &d.sel)) != BH_OK ||
       (rc = upload_vec(t.wt, &d.wt)) != BH_OK ||
       (rc = upload_vec(t.p_first, &d.p_first)) != BH_OK ||
+      (rc = upload_vec(t.wave_p, &d.wave_p)) != BH_OK ||
       (rc = upload_vec(t.deg_start, &d.deg_start)) != BH_OK ||
       (rc = upload_vec(t.deg_off, &d.deg_off)) != BH_OK) {
     free_band(d);

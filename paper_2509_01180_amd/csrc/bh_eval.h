@@ -9,6 +9,12 @@
 
 #include "bh_special.h"
 
+// Phases e^{-i p sigma} by FP64 sincos per p-group (1) or by a running
+// product along the wave's ascending p-list (0); build-time parameter.
+#ifndef BH_SCORE_PHASE_SINCOS
+#define BH_SCORE_PHASE_SINCOS 0
+#endif
+
 namespace bh {
 
 struct cplx {
@@ -67,28 +73,44 @@ struct Acc {
     RB = fma(msa_, EA, fma(u_, RA, -RB));                                     \
   } while (0)
 
-// Partial sums of one wave over its classes p = wave, wave + W, ...
+// Partial sums of one wave over the classes of its p-groups: plist holds
+// [count, p_1, ..., p_count] (a wave's share of the longest-first split).
 //
 // Chain loop: four entries per round.  The four X and rec entries of a
 // round are wave-uniform and fetched together with scalar loads (one wait
 // per round: scalar loads return out of order, so a wait drains them all);
 // (ea, ra) and (eb, rb) hold e, de/dbeta of two consecutive degrees and each
 // step overwrites the older pair, so no register moves are needed.
-BH_HD inline Acc eval_wave(const Angles& A, int wave, int W, int L,
+BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, int L,
                            const int32_t* __restrict__ p_first,
                            const double* __restrict__ rec, const double* __restrict__ X) {
   Acc acc = {0.0, 0.0, 0.0, 0.0};
   const double msb = -A.sb;
-  // Phi_p = e^{-i p sigma} by a running product over this wave's p values
-  double s0, c0, sw, cw;
-  sincos((double)wave * A.sigma, &s0, &c0);
-  sincos((double)W * A.sigma, &sw, &cw);
-  cplx Phi = {c0, -s0};
-  const cplx PhiW = {cw, -sw};
-  for (int p = wave; p <= 2 * L; p += W) {
-    // c^{max(p-1,0)}, c^p, c^{p+1}
-    double cpm1 = 1.0;
+  const int np = plist[0];
+#if !BH_SCORE_PHASE_SINCOS
+  // Phi = e^{-i pc sigma} and cpm1 = c^{max(pc-1,0)}, advanced along the
+  // ascending p-list one degree at a time.
+  double s1, c1;
+  sincos(A.sigma, &s1, &c1);
+  const cplx E1 = {c1, -s1};
+  cplx Phi = {1.0, 0.0};
+  double cpm1 = 1.0;
+  int pc = 0;
+#endif
+  for (int j = 0; j < np; ++j) {
+    const int p = plist[1 + j];
+#if BH_SCORE_PHASE_SINCOS
+    double sp, cpp;
+    sincos((double)p * A.sigma, &sp, &cpp);
+    const cplx Phi = {cpp, -sp};          // e^{-i p sigma}
+    double cpm1 = 1.0;                    // c^{max(p-1,0)}
     for (int i = 1; i < p; ++i) cpm1 *= A.c;
+#else
+    for (; pc < p; ++pc) {
+      Phi = cmul(Phi, E1);
+      cpm1 = (pc >= 1) ? cpm1 * A.c : 1.0;
+    }
+#endif
     const double cp = (p > 0) ? cpm1 * A.c : 1.0;
     const double cpp1 = cp * A.c;
     int off = p_first[p];
@@ -143,7 +165,6 @@ BH_HD inline Acc eval_wave(const Angles& A, int wave, int W, int L,
       sqm1 = (q == 0) ? A.s : sqm1 * A.s2;
       sq *= A.s2;
     }
-    Phi = cmul(Phi, PhiW);
   }
   return acc;
 }

@@ -45,6 +45,7 @@ struct DevBand {
   int32_t* sel = nullptr;       // [n_entries][4]
   double* wt = nullptr;         // [n_entries][2]
   int32_t* p_first = nullptr;   // [2L+2]
+  int32_t* wave_p = nullptr;    // work split per wave count (BandTables::wave_p)
   int32_t* deg_start = nullptr; // [L+2]
   int32_t* deg_off = nullptr;
 };

@@ -36,6 +36,21 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 6.28318530717958647692;
 constexpr double kSin2Floor = 1e-6;
 
+// Occupancy target of the score kernels (waves per SIMD; 0 = compiler's
+// choice) and an optional fixed wave count per workgroup (0 = automatic);
+// build-time tuning parameters.
+#ifndef BH_SCORE_WAVES_PER_EU
+#define BH_SCORE_WAVES_PER_EU 6
+#endif
+#ifndef BH_SCORE_FIXED_W
+#define BH_SCORE_FIXED_W 0
+#endif
+#if BH_SCORE_WAVES_PER_EU > 0
+#define BH_SCORE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(BH_SCORE_WAVES_PER_EU)))
+#else
+#define BH_SCORE_OCCUPANCY
+#endif
+
 // ------------------------------------------------------------ cross-power --
 
 // Dense xi^l_{mn} for the ABI: thread per (particle, entry of E(L)).
@@ -153,7 +168,8 @@ __device__ inline void wrap_euler(double& a, double& b, double& g) {
 }
 
 template <int W>
-__global__ __launch_bounds__(64 * W) void k_correlate(const int32_t* __restrict__ p_first,
+__global__ __launch_bounds__(64 * W) BH_SCORE_OCCUPANCY void k_correlate(
+    const int32_t* __restrict__ p_first, const int32_t* __restrict__ wave_p,
                                                       const double* __restrict__ rec,
                                                       const double* __restrict__ X, int64_t n_entries,
                                                       int L, const double* __restrict__ euler, int R,
@@ -173,7 +189,7 @@ __global__ __launch_bounds__(64 * W) void k_correlate(const int32_t* __restrict_
     ga = eu[2];
   }
   const Angles A = prep(al, be, ga);
-  const Acc mine = eval_wave(A, wave, W, L, p_first, rec, X + pb * n_entries * 4);
+  const Acc mine = eval_wave(A, wave_p + wave * (2 * L + 2), L, p_first, rec, X + pb * n_entries * 4);
   const Acc t = reduce_waves(mine, buf, wave, lane, W);
   if (wave == 0 && active) {
     score[pb * R + r] = t.S;
@@ -193,7 +209,8 @@ __global__ __launch_bounds__(64 * W) void k_correlate(const int32_t* __restrict_
 enum { ST_XA, ST_XB, ST_XG, ST_S, ST_GA, ST_GB, ST_GG, ST_ETA, ST_TA, ST_TB, ST_TG, ST_N };
 
 template <int W>
-__global__ __launch_bounds__(64 * W) void k_march(const int32_t* __restrict__ p_first,
+__global__ __launch_bounds__(64 * W) BH_SCORE_OCCUPANCY void k_march(
+    const int32_t* __restrict__ p_first, const int32_t* __restrict__ wave_p,
                                                   const double* __restrict__ rec,
                                                   const double* __restrict__ X, int64_t n_entries,
                                                   int L, const double* __restrict__ Wb, int P,
@@ -226,7 +243,7 @@ __global__ __launch_bounds__(64 * W) void k_march(const int32_t* __restrict__ p_
   __syncthreads();
   for (int t = 0; t <= steps; ++t) {
     const Angles A = prep(st[ST_TA * 64 + lane], st[ST_TB * 64 + lane], st[ST_TG * 64 + lane]);
-    const Acc mine = eval_wave(A, wave, W, L, p_first, rec, Xp);
+    const Acc mine = eval_wave(A, wave_p + wave * (2 * L + 2), L, p_first, rec, Xp);
     red[(wave * 4 + 0) * 64 + lane] = mine.S;
     red[(wave * 4 + 1) * 64 + lane] = mine.ga;
     red[(wave * 4 + 2) * 64 + lane] = mine.gb;
@@ -317,13 +334,14 @@ __global__ __launch_bounds__(64) void k_select(const double* __restrict__ state,
 }
 
 int pick_waves(int64_t groups, int L) {
-  // About 4096 resident waves fill the chip (256 CUs x 4 SIMDs x 4 waves
-  // at the score kernels' register use): few workgroups get more waves
-  // each.  Classes are split by p = 0..2L, so more than 2L+1 waves idle.
-  int W = 4;
-  if (groups * 8 <= 4096) W = 8;
-  if (groups * 16 <= 4096) W = 16;
-  while (W > 4 && W > 2 * L + 1) W /= 2;
+  if (BH_SCORE_FIXED_W > 0) return BH_SCORE_FIXED_W;
+  // Measured on MI355X (1000 particles x 64 restarts, bands 8..32): 12 waves
+  // per workgroup at 6 waves per SIMD (two workgroups per CU) is fastest for
+  // L > 8, 4 waves for L <= 8; small batches spread one particle over 16
+  // waves.  More than 2L+1 waves would have no p-group to work on.
+  int W = (L <= 8) ? 4 : 12;
+  if (groups < 256) W = 16;
+  while (W > 2 * L + 1 && W > 4) W = (W == 16) ? 12 : (W == 12 ? 8 : (W == 8 ? 6 : W - 1));
   return W;
 }
 
@@ -332,7 +350,8 @@ void launch_correlate_w(bh_plan* p, dim3 grid, hipStream_t s, const DevBand& ban
                         int L, const double* euler, int R, double* score, double* grad) {
   ProfScope ps(p, "correlate_L" + std::to_string(L), s,
                (int64_t)grid.y * R * band.n_entries);
-  hipLaunchKernelGGL(k_correlate<W>, grid, dim3(64 * W), 0, s, band.p_first, band.rec, X,
+  hipLaunchKernelGGL(k_correlate<W>, grid, dim3(64 * W), 0, s, band.p_first,
+                     band.wave_p + wave_block_offset(L, W), band.rec, X,
                      band.n_entries, L, euler, R, score, grad);
 }
 
@@ -342,7 +361,8 @@ void launch_march_w(bh_plan* p, dim3 grid, hipStream_t s, const DevBand& band, c
                     double* sscore) {
   ProfScope ps(p, "march_L" + std::to_string(L), s,
                (int64_t)grid.y * P * (o.steps_per_band + 1) * band.n_entries);
-  hipLaunchKernelGGL(k_march<W>, grid, dim3(64 * W), 0, s, band.p_first, band.rec, X,
+  hipLaunchKernelGGL(k_march<W>, grid, dim3(64 * W), 0, s, band.p_first,
+                     band.wave_p + wave_block_offset(L, W), band.rec, X,
                      band.n_entries, L, Wb, P, o.steps_per_band, o.step_init, o.step_grow,
                      o.step_shrink, state, sscore);
 }
@@ -382,9 +402,15 @@ int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const floa
   const int64_t chunks = (R + 63) / 64;
   const dim3 grid((unsigned)chunks, (unsigned)B);
   const int W = pick_waves(chunks * B, band.L);
-  if (W == 16) launch_correlate_w<16>(p, grid, s, band, X, band.L, euler, R, score, grad);
-  else if (W == 8) launch_correlate_w<8>(p, grid, s, band, X, band.L, euler, R, score, grad);
-  else launch_correlate_w<4>(p, grid, s, band, X, band.L, euler, R, score, grad);
+  switch (W) {
+    case 16: launch_correlate_w<16>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
+    case 12: launch_correlate_w<12>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
+    case 10: launch_correlate_w<10>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
+    case 8: launch_correlate_w<8>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
+    case 6: launch_correlate_w<6>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
+    case 5: launch_correlate_w<5>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
+    default: launch_correlate_w<4>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
+  }
   BH_HIP(hipGetLastError());
   return BH_OK;
 }
@@ -420,9 +446,15 @@ int launch_align(bh_plan* p, const float* a, const float* b, int64_t B, const bh
     }
     BH_HIP(hipGetLastError());
     const int W = pick_waves(chunks * B, band->L);
-    if (W == 16) launch_march_w<16>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore);
-    else if (W == 8) launch_march_w<8>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore);
-    else launch_march_w<4>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore);
+    switch (W) {
+      case 16: launch_march_w<16>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
+      case 12: launch_march_w<12>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
+      case 10: launch_march_w<10>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
+      case 8: launch_march_w<8>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
+      case 6: launch_march_w<6>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
+      case 5: launch_march_w<5>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
+      default: launch_march_w<4>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
+    }
     BH_HIP(hipGetLastError());
   }
   {

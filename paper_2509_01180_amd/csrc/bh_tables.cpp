@@ -119,6 +119,15 @@ std::vector<int32_t> ball_voxels(int N) {
   return v;
 }
 
+int64_t wave_block_offset(int L, int W) {
+  int64_t off = 0;
+  for (int wi = 0; wi < kNumWaveChoices; ++wi) {
+    if (kWaveChoices[wi] == W) return off;
+    off += (int64_t)kWaveChoices[wi] * (2 * L + 2);
+  }
+  return -1;
+}
+
 BandTables band_tables(int L, int Lmax) {
   BandTables t;
   t.L = L;
@@ -175,6 +184,38 @@ BandTables band_tables(int L, int Lmax) {
     }
   }
   t.p_first[2 * L + 1] = (int32_t)t.n_entries;
+
+  // Longest-first assignment of p-groups to waves.  Cost of a group: its
+  // recurrence entries and class epilogues, in instructions of the kernel.
+  std::vector<std::pair<int64_t, int>> cost;
+  for (int p = 0; p <= 2 * L; ++p) {
+    const int64_t entries = t.p_first[p + 1] - t.p_first[p];
+    const int64_t classes = (2 * L - p) / 2 + 1;
+    cost.push_back({14 * entries + 35 * classes, p});
+  }
+  std::sort(cost.begin(), cost.end(), [](const std::pair<int64_t, int>& a,
+                                         const std::pair<int64_t, int>& b) {
+    return a.first != b.first ? a.first > b.first : a.second < b.second;
+  });
+  const int row = 2 * L + 2;
+  for (int wi = 0; wi < kNumWaveChoices; ++wi) {
+    const int W = kWaveChoices[wi];
+    std::vector<int64_t> load(W, 0);
+    std::vector<std::vector<int>> lists(W);
+    for (const auto& c : cost) {
+      int best = 0;
+      for (int w = 1; w < W; ++w)
+        if (load[w] < load[best]) best = w;
+      load[best] += c.first;
+      lists[best].push_back(c.second);
+    }
+    for (int w = 0; w < W; ++w) {
+      std::sort(lists[w].begin(), lists[w].end());
+      t.wave_p.push_back((int32_t)lists[w].size());
+      for (int i = 0; i < row - 1; ++i)
+        t.wave_p.push_back(i < (int)lists[w].size() ? lists[w][i] : 0);
+    }
+  }
 
   // radial entries of band L grouped by degree, as offsets in the Lmax layout
   const IndexSet& big = index_set(Lmax);

@@ -65,10 +65,20 @@ struct BandTables {
   std::vector<int32_t> sel;       // [n_entries][4]
   std::vector<double> wt;         // [n_entries][2]
   std::vector<int32_t> p_first;   // [2L+2] first entry of the classes with this p
+  // Work split of the classes over the W waves of a workgroup, for each W in
+  // kWaveChoices: the p-groups are assigned longest first to the least
+  // loaded wave.  Block of W rows of (2L+2) ints: [count, p_1, ..., p_count].
+  std::vector<int32_t> wave_p;
   // radial entries of the band grouped by degree (for the cross-power sums)
   std::vector<int32_t> deg_start; // [L+2]
   std::vector<int32_t> deg_off;   // coefficient offsets of (l, k) with lambda < cutoff(L)
 };
+
+// Wave counts per workgroup for which band_tables prepares a work split.
+constexpr int kWaveChoices[] = {4, 5, 6, 8, 10, 12, 16};
+constexpr int kNumWaveChoices = 7;
+// Offset of the block of W (one of kWaveChoices) in BandTables::wave_p.
+int64_t wave_block_offset(int L, int W);
 
 // Tables of band L; coefficient offsets refer to the layout of index_set(Lmax).
 BandTables band_tables(int L, int Lmax);
