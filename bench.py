@@ -38,6 +38,7 @@ import synth  # noqa: E402
 
 PEAK_FP64_VECTOR = 78.6e12     # MI355X dense FP64 vector, FLOP/s (FMA = 2)
 PEAK_FP32_MFMA = 157.3e12      # MI355X dense FP32 matrix, FLOP/s
+PEAK_BF16_MFMA = 2.5e15        # MI355X dense BF16 matrix, FLOP/s
 PEAK_HBM = 8.0e12              # bytes/s
 
 # Operation counts of the score/gradient evaluation:
@@ -112,6 +113,9 @@ def main():
     ap.add_argument("--batch", type=int, default=None, help="particles per step (default 1000)")
     ap.add_argument("--cpu-sample", type=int, default=1, help="particles timed on the oracle (0: skip)")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--precision", choices=("plain", "bf16x3"), default="plain",
+                    help="plain: FP32 expansion; bf16x3: BF16 MFMA expansion for the coarse bands "
+                         "and split-BF16 refined coefficients for the final band")
     ap.add_argument("--calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed "
                          "region (reference kernel for hardware traffic counters)")
@@ -147,9 +151,17 @@ def main():
     torch.cuda.synchronize()
     print(f"# plan built in {t_plan:.2f} s", file=sys.stderr, flush=True)
 
+    a_coarse = torch.empty_like(a) if args.precision == "bf16x3" else None
+
     def step():
-        plan.expand(vols, out=a)
-        return plan.align(a, b, w.bands, starts, w.steps)
+        if args.precision == "plain":
+            plan.expand(vols, out=a)
+            return plan.align(a, b, w.bands, starts, w.steps)
+        # precision form: BF16 coefficients for the coarse bands, refined ones
+        # for the final band, continuing from every restart's end point
+        plan.expand_ex(vols, "bf16x3", out=a, coarse=a_coarse)
+        _e, _s, ends, _sc = plan.align(a_coarse, b, w.bands[:-1], starts, w.steps, return_all=True)
+        return plan.align(a, b, w.bands[-1:], ends, w.steps)
 
     for _ in range(args.warmup):
         step()
@@ -174,7 +186,7 @@ def main():
 
     # per-kernel event timing over the timed region
     kern = {}
-    for name in ("gather", "gemm", "reduce", "xi_classes", "band_weight", "march_L*", "select"):
+    for name in ("gather*", "gemm*", "reduce", "xi_classes", "band_weight", "march_L*", "select"):
         n, ms, work = plan.profile_read(name)
         kern[name.rstrip("*")] = {"launches": n, "ms_per_step": ms / max(args.steps, 1)}
     n_m, ms_m, _ = plan.profile_read("march_L*")
@@ -188,11 +200,12 @@ def main():
     achieved = flops_per_launch / avg_launch_s
     traffic = load_traffic(score_kernel_sources_hash())
 
-    n_g, ms_g, _ = plan.profile_read("gemm")
+    n_g, ms_g, _ = plan.profile_read("gemm*")
     from paper_2509_01180_amd.api import ball_voxels
     V = ball_voxels(w.N)
-    gemm_flops = 2.0 * B * V * plan.C
+    gemm_flops = 2.0 * B * V * plan.C * (1 if args.precision == "plain" else 3)
     gemm_achieved = gemm_flops / ((ms_g / n_g) / 1e3)
+    gemm_peak = PEAK_FP32_MFMA if args.precision == "plain" else PEAK_BF16_MFMA
 
     # accuracy against the planted rotations (context; the wedge and noise set it)
     eu_h = eu.cpu().numpy()
@@ -213,10 +226,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32/f64",
+        "dtype": "f32/f64" if args.precision == "plain" else "bf16(fp32 acc)/f64",
         "data": "synthetic",
         "config": {
-            "workload": f"plain path: {B} x 64^3 fp32 subtomograms vs one 50-blob template, "
+            "workload": f"{'plain path' if args.precision == 'plain' else 'precision form (bf16x3 expansion)'}: {B} x 64^3 fp32 subtomograms vs one 50-blob template, "
                         "L=32, bands 8-16-24-32, 20 ascent steps/band, 64 restarts, "
                         "+/-60 deg wedge, SNR 0.05",
             "global_batch": B, "box": w.N, "L_max": w.L_max, "bands": list(w.bands),
@@ -235,9 +248,10 @@ def main():
             "avg_launch_ms": round(avg_launch_s * 1e3, 4),
         },
         "roofline_expand": {
-            "kernel": "k_gemm_f32", "bound": "mfma",
-            "achieved": round(gemm_achieved / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12,
-            "unit": "TFLOP/s", "frac": round(gemm_achieved / PEAK_FP32_MFMA, 4),
+            "kernel": "k_gemm_f32" if args.precision == "plain" else "k_gemm_bf16 (3 products)",
+            "bound": "mfma",
+            "achieved": round(gemm_achieved / 1e12, 3), "peak": gemm_peak / 1e12,
+            "unit": "TFLOP/s", "frac": round(gemm_achieved / gemm_peak, 4),
             "avg_launch_ms": round(ms_g / n_g, 4),
         },
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in kern.items()},

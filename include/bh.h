@@ -116,6 +116,21 @@ int64_t bh_plan_num_coeffs(const bh_plan* p, int L);
  * ------------------------------------------------------------------- */
 int bh_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, void* stream);
 
+/* Expansion with a choice of arithmetic (same layouts as bh_expand):
+ *  BH_EXPAND_FP32:   as bh_expand (FP32 MFMA, FP32 accumulation).
+ *  BH_EXPAND_BF16:   basis and samples rounded to BF16, BF16 MFMA with FP32
+ *                    accumulation; relative error ~2^-8 per term.
+ *  BH_EXPAND_BF16X3: each FP32 value split as hi + lo (both BF16); the sum
+ *                    of hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32
+ *                    accumulation, close to FP32 accuracy.  If `coarse` is
+ *                    not NULL (dev float[B][C(L_max)][2]) the hi*hi part
+ *                    alone (the BF16 result) is written there as well.
+ * The BF16 basis (2 bytes x V x C for hi and again for lo) is built on the
+ * first BF16 call and kept by the plan. */
+enum { BH_EXPAND_FP32 = 0, BH_EXPAND_BF16 = 1, BH_EXPAND_BF16X3 = 2 };
+int bh_expand_ex(bh_plan* p, const float* vols, int64_t B, int mode, float* coeffs, float* coarse,
+                 void* stream);
+
 /* ---------------------------------------------------------------------
  * Cross-power of Eq. (2) for band L (0 <= L <= L_max).
  * a:  dev float[B][C(L_max)][2]  particle coefficients

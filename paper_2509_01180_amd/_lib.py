@@ -15,6 +15,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("BH_LIBRARY") or os.path.join(_PKG, "libbh.so")
 
 BH_OK, BH_EINVAL, BH_ENOMEM, BH_EDEVICE, BH_EUNSUPPORTED = 0, -1, -2, -3, -4
+BH_EXPAND_FP32, BH_EXPAND_BF16, BH_EXPAND_BF16X3 = 0, 1, 2
 BH_MAX_L = 64
 BH_MAX_N = 256
 
@@ -55,6 +56,7 @@ SIGNATURES = {
     "bh_plan_destroy": (None, [_P]),
     "bh_plan_num_coeffs": (_I64, [_P, _I]),
     "bh_expand": (_I, [_P, _P, _I64, _P, _P]),
+    "bh_expand_ex": (_I, [_P, _P, _I64, _I, _P, _P, _P]),
     "bh_cross_power": (_I, [_P, _P, _P, _I64, _I, _P, _P]),
     "bh_correlate": (_I, [_P, _P, _P, _I64, _I, _P, _I, _P, _P, _P]),
     "bh_align": (_I, [_P, _P, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),

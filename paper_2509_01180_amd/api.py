@@ -136,6 +136,25 @@ class Plan:
         check(lib().bh_expand(self._h, _ptr(vols), B, _ptr(out), _stream()), "bh_expand")
         return out
 
+    def expand_ex(self, vols: torch.Tensor, mode: str = "fp32", out: torch.Tensor | None = None,
+                  coarse: torch.Tensor | None = None) -> torch.Tensor:
+        """Expansion in mode "fp32", "bf16" or "bf16x3" (see bh_expand_ex).
+
+        With mode "bf16x3" and a `coarse` tensor [B, C, 2], the BF16 (hi*hi)
+        result is written there too.
+        """
+        modes = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+        B = vols.shape[0]
+        _dev(vols, torch.float32, (B, self.N, self.N, self.N), "vols")
+        if out is None:
+            out = torch.empty((B, self.C, 2), dtype=torch.float32, device=vols.device)
+        _dev(out, torch.float32, (B, self.C, 2), "out")
+        if coarse is not None:
+            _dev(coarse, torch.float32, (B, self.C, 2), "coarse")
+        check(lib().bh_expand_ex(self._h, _ptr(vols), B, modes[mode], _ptr(out), _ptr(coarse),
+                                 _stream()), "bh_expand_ex")
+        return out
+
     def cross_power(self, a: torch.Tensor, b: torch.Tensor, L: int) -> torch.Tensor:
         """xi [B, E(L), 2] float64 (blocks l, row-major [m][n])."""
         B = a.shape[0]

@@ -249,7 +249,8 @@ void bh_plan_destroy(bh_plan* p) {
   if (!p) return;
   DeviceGuard g(p->device);
   (void)hipDeviceSynchronize();
-  for (void* q : {(void*)p->psi, (void*)p->vidx, (void*)p->csrc, (void*)p->csgn})
+  for (void* q : {(void*)p->psi, (void*)p->psi_h, (void*)p->psi_l, (void*)p->vidx, (void*)p->csrc,
+                  (void*)p->csgn})
     if (q) (void)hipFree(q);
   for (Buffer* b : {&p->gathered, &p->partial, &p->xi_scr, &p->state_scr, &p->misc_scr})
     if (b->ptr) (void)hipFree(b->ptr);
@@ -313,6 +314,25 @@ int bh_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, void* str
     DeviceGuard g(p->device);
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
     return launch_expand(p, vols, B, coeffs, (hipStream_t)stream);
+  });
+}
+
+int bh_expand_ex(bh_plan* p, const float* vols, int64_t B, int mode, float* coeffs, float* coarse,
+                 void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (B < 0 || B > (1LL << 21)) return set_error(BH_EINVAL, "batch size out of range");
+  if (mode != BH_EXPAND_FP32 && mode != BH_EXPAND_BF16 && mode != BH_EXPAND_BF16X3)
+    return set_error(BH_EINVAL, "unknown expansion mode");
+  if (coarse && mode != BH_EXPAND_BF16X3)
+    return set_error(BH_EINVAL, "a coarse output needs the BF16X3 mode");
+  if (B == 0) return BH_OK;
+  if (!vols || !coeffs) return set_error(BH_EINVAL, "NULL buffer");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    if (mode == BH_EXPAND_FP32) return launch_expand(p, vols, B, coeffs, (hipStream_t)stream);
+    return launch_expand_bf16(p, vols, B, mode == BH_EXPAND_BF16X3, coeffs, coarse,
+                              (hipStream_t)stream);
   });
 }
 

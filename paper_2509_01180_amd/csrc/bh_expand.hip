@@ -39,6 +39,29 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ vols, 
   }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (linear id mod 8),
+// each with its own L2.  When the coefficient tiles divide evenly, XCD x
+// takes coefficient tiles [x*nt/8, (x+1)*nt/8) for every particle tile and
+// split, ordered so that co-resident workgroups share K-slices: particle
+// tiles fastest (they share the basis slice), then this XCD's coefficient
+// tiles (they share the volume slice), then splits.  Each basis column is
+// then fetched by one XCD only.
+__device__ inline void gemm_tile(int64_t bid, int64_t mt, int64_t nt, int64_t ns, int64_t& m,
+                                 int64_t& n, int64_t& sp) {
+  if (nt % 8 == 0) {
+    const int64_t xcd = bid % 8, local = bid / 8, ntx = nt / 8;
+    m = local % mt;
+    const int64_t r = local / mt;
+    n = xcd * ntx + r % ntx;
+    sp = r / ntx;
+  } else {
+    m = bid % mt;
+    const int64_t r = bid / mt;
+    n = r % nt;
+    sp = r / nt;
+  }
+}
+
 // part[s][m][n] = sum_{k in split s} Ft[k][m] Psi[k][n].
 // 4 waves in a 2x2 arrangement, each 64x64 = 2x2 MFMA 32x32 tiles.
 // MFMA 32x32x2 f32 operand layout: lane L supplies A[L%32][L/32] and
@@ -46,12 +69,14 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ vols, 
 __global__ __launch_bounds__(256, 2) void k_gemm_f32(const float* __restrict__ Ft,
                                                      const float* __restrict__ Psi,
                                                      float* __restrict__ part, int64_t M_pad,
-                                                     int64_t C_pad, int nk) {
+                                                     int64_t C_pad, int nk, int nsplit) {
   __shared__ float As[2][BK][BM];
   __shared__ float Bs[2][BK][BN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
-  const int64_t k_begin = (int64_t)blockIdx.z * nk * BK;
+  int64_t tm, tn, ts;
+  gemm_tile(blockIdx.x, M_pad / BM, C_pad / BN, nsplit, tm, tn, ts);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int64_t k_begin = ts * nk * BK;
   const int lr = tid >> 5, lc = (tid & 31) * 4;
   const float* pa = Ft + (k_begin + lr) * M_pad + m0 + lc;
   const float* pb = Psi + (k_begin + lr) * C_pad + n0 + lc;
@@ -106,7 +131,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(const float* __restrict__ F
   }
 #undef BH_GLOAD
 #undef BH_SSTORE
-  float* out = part + (int64_t)blockIdx.z * M_pad * C_pad;
+  float* out = part + ts * M_pad * C_pad;
   const int64_t row0 = m0 + wm + 4 * hl, col0 = n0 + wn + ll;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -162,8 +187,8 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
   BH_HIP(hipGetLastError());
   {
   ProfScope ps(p, "gemm", s, B);
-  hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)mt, (unsigned)nt, (unsigned)nsplit), dim3(256), 0, s,
-                     Ft, p->psi, part, M_pad, p->C_pad, nk);
+  hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)(mt * nt * nsplit)), dim3(256), 0, s, Ft, p->psi,
+                     part, M_pad, p->C_pad, nk, nsplit);
   }
   BH_HIP(hipGetLastError());
   const int64_t tot = B * p->C;

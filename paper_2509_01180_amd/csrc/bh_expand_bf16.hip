@@ -1,0 +1,313 @@
+// Expansion on BF16 MFMA with FP32 accumulation (Sec. II-A, the coefficients
+// a = h^3 Psi^T f), and its split-BF16 refinement.
+//
+// Every FP32 value x is split as x = hi + lo + r with hi = bf16(x),
+// lo = bf16(x - hi), |r| <= 2^-16 |x| or so.  Then
+//   coarse  = Psi_hi^T F_hi                      (relative error ~ 2^-8)
+//   refined = coarse + Psi_hi^T F_lo + Psi_lo^T F_hi   (~ 2^-16: FP32-level)
+// Both are computed by one kernel with two accumulator sets; the three
+// products use v_mfma_f32_32x32x16_bf16.
+//
+//   k_psi_split : Psi[V_pad][C_pad] FP32 -> Ph, Pl [C_pad][V_pad] BF16 (once per plan)
+//   k_gather_split: vols -> Fh, Fl [M_pad][V_pad] BF16 (ball voxels, zero padded)
+//   k_gemm_bf16 : split-K partial sums, 128x128 tiles, K step 32 voxels
+//   k_reduce2   : sums splits, scatters to the complex layout
+//
+// Operands are K-contiguous rows (particles, coefficients), staged in LDS
+// with rows padded to 40 BF16 (80 bytes) so that 16-byte fragment reads of
+// eight consecutive rows fall in distinct banks.  A lane's fragment is eight
+// consecutive voxels of one row; the same voxel-to-lane map is used for both
+// operands, so the sum over voxels is exact whatever order the instruction
+// takes it in.
+#include "bh_internal.h"
+
+namespace bh {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 128, BN = 128, BK = 32, ROW = 40;
+
+// FP32 -> BF16 bits, round to nearest even (inputs are finite).
+__device__ inline uint16_t bf16_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Ph[c][v], Pl[c][v] from Psi[v][c]: 32x32 LDS transpose and split.
+__global__ __launch_bounds__(256) void k_psi_split(const float* __restrict__ psi, int64_t V_pad,
+                                                   int64_t C_pad, uint16_t* __restrict__ ph,
+                                                   uint16_t* __restrict__ pl) {
+  __shared__ float tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t v0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) tile[ty + 8 * i][tx] = psi[(v0 + ty + 8 * i) * C_pad + c0 + tx];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float x = tile[tx][ty + 8 * i];
+    const uint16_t h = bf16_bits(x);
+    const int64_t o = (c0 + ty + 8 * i) * V_pad + v0 + tx;
+    ph[o] = h;
+    pl[o] = bf16_bits(x - bf16_value(h));
+  }
+}
+
+// Fh[b][v], Fl[b][v] = split of vols[b][vidx[v]] (0 outside v < V, b < B).
+__global__ __launch_bounds__(256) void k_gather_split(const float* __restrict__ vols,
+                                                      int64_t vol_stride, int64_t B,
+                                                      const int32_t* __restrict__ vidx, int64_t V,
+                                                      int64_t V_pad, int64_t M_pad,
+                                                      uint16_t* __restrict__ fh,
+                                                      uint16_t* __restrict__ fl) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= V_pad) return;
+  const int32_t lin = (v < V) ? vidx[v] : 0;
+  for (int64_t b = blockIdx.y; b < M_pad; b += gridDim.y) {
+    const float x = (v < V && b < B) ? vols[b * vol_stride + lin] : 0.0f;
+    const uint16_t h = bf16_bits(x);
+    fh[b * V_pad + v] = h;
+    fl[b * V_pad + v] = bf16_bits(x - bf16_value(h));
+  }
+}
+
+// Tile placement over the XCDs, as for the FP32 GEMM (see bh_expand.hip).
+__device__ inline void tile_of(int64_t bid, int64_t mt, int64_t nt, int64_t ns, int64_t& m,
+                               int64_t& n, int64_t& sp) {
+  if (nt % 8 == 0) {
+    const int64_t xcd = bid % 8, local = bid / 8, ntx = nt / 8;
+    m = local % mt;
+    const int64_t r = local / mt;
+    n = xcd * ntx + r % ntx;
+    sp = r / ntx;
+  } else {
+    m = bid % mt;
+    const int64_t r = bid / mt;
+    n = r % nt;
+    sp = r / nt;
+  }
+}
+
+// COARSE: part_c += Fh Ph^T.  CORR: part_r += Fh Pl^T + Fl Ph^T.
+template <bool COARSE, bool CORR>
+__global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict__ fh,
+                                                      const uint16_t* __restrict__ fl,
+                                                      const uint16_t* __restrict__ ph,
+                                                      const uint16_t* __restrict__ pl,
+                                                      float* __restrict__ part_c,
+                                                      float* __restrict__ part_r, int64_t M_pad,
+                                                      int64_t C_pad, int64_t V_pad, int nk,
+                                                      int nsplit) {
+  constexpr bool LO = CORR;
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][BM][ROW];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][BN][ROW];
+  __shared__ __attribute__((aligned(16))) uint16_t Al[LO ? 2 : 1][LO ? BM : 1][ROW];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[LO ? 2 : 1][LO ? BN : 1][ROW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t tm, tn, ts;
+  tile_of(blockIdx.x, M_pad / BM, C_pad / BN, nsplit, tm, tn, ts);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int64_t k_begin = ts * (int64_t)nk * BK;
+  // global -> LDS: 128 rows x 32 voxels = 512 chunks of 8 BF16; two per thread
+  const int r0 = tid >> 2, r1 = r0 + 64, cc = (tid & 3) * 8;
+  const uint16_t* ga_h = fh + (m0 + r0) * V_pad + k_begin + cc;
+  const uint16_t* gb_h = ph + (n0 + r0) * V_pad + k_begin + cc;
+  const uint16_t* ga_l = LO ? fl + (m0 + r0) * V_pad + k_begin + cc : nullptr;
+  const uint16_t* gb_l = LO ? pl + (n0 + r0) * V_pad + k_begin + cc : nullptr;
+  const int64_t off64a = 64 * V_pad, off64b = 64 * V_pad;
+  uint4 xah0, xah1, xbh0, xbh1, xal0, xal1, xbl0, xbl1;
+#define BH_LOAD(kt)                                                                   \
+  do {                                                                                \
+    const int64_t ko = (int64_t)(kt) * BK;                                            \
+    xah0 = *reinterpret_cast<const uint4*>(ga_h + ko);                                \
+    xah1 = *reinterpret_cast<const uint4*>(ga_h + off64a + ko);                       \
+    xbh0 = *reinterpret_cast<const uint4*>(gb_h + ko);                                \
+    xbh1 = *reinterpret_cast<const uint4*>(gb_h + off64b + ko);                       \
+    if (LO) {                                                                         \
+      xal0 = *reinterpret_cast<const uint4*>(ga_l + ko);                              \
+      xal1 = *reinterpret_cast<const uint4*>(ga_l + off64a + ko);                     \
+      xbl0 = *reinterpret_cast<const uint4*>(gb_l + ko);                              \
+      xbl1 = *reinterpret_cast<const uint4*>(gb_l + off64b + ko);                     \
+    }                                                                                 \
+  } while (0)
+#define BH_STORE(buf)                                                                 \
+  do {                                                                                \
+    *reinterpret_cast<uint4*>(&Ah[buf][r0][cc]) = xah0;                               \
+    *reinterpret_cast<uint4*>(&Ah[buf][r1][cc]) = xah1;                               \
+    *reinterpret_cast<uint4*>(&Bh[buf][r0][cc]) = xbh0;                               \
+    *reinterpret_cast<uint4*>(&Bh[buf][r1][cc]) = xbh1;                               \
+    if (LO) {                                                                         \
+      *reinterpret_cast<uint4*>(&Al[LO ? buf : 0][LO ? r0 : 0][cc]) = xal0;           \
+      *reinterpret_cast<uint4*>(&Al[LO ? buf : 0][LO ? r1 : 0][cc]) = xal1;           \
+      *reinterpret_cast<uint4*>(&Bl[LO ? buf : 0][LO ? r0 : 0][cc]) = xbl0;           \
+      *reinterpret_cast<uint4*>(&Bl[LO ? buf : 0][LO ? r1 : 0][cc]) = xbl1;           \
+    }                                                                                 \
+  } while (0)
+  floatx16 c00 = {}, c01 = {}, c10 = {}, c11 = {};
+  floatx16 d00 = {}, d01 = {}, d10 = {}, d11 = {};
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int hl = lane >> 5, ll = lane & 31;
+  BH_LOAD(0);
+  BH_STORE(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) BH_LOAD(kt + 1);
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ++ks) {
+      const int kc = 16 * ks + 8 * hl;
+      const bf16x8 ah0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[cur][wm + ll][kc]));
+      const bf16x8 ah1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[cur][wm + 32 + ll][kc]));
+      const bf16x8 bh0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[cur][wn + ll][kc]));
+      const bf16x8 bh1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[cur][wn + 32 + ll][kc]));
+      if (COARSE) {
+        c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bh0, c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bh1, c01, 0, 0, 0);
+        c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bh0, c10, 0, 0, 0);
+        c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bh1, c11, 0, 0, 0);
+      }
+      if (CORR) {
+        const bf16x8 al0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[LO ? cur : 0][LO ? wm + ll : 0][kc]));
+        const bf16x8 al1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[LO ? cur : 0][LO ? wm + 32 + ll : 0][kc]));
+        const bf16x8 bl0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[LO ? cur : 0][LO ? wn + ll : 0][kc]));
+        const bf16x8 bl1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[LO ? cur : 0][LO ? wn + 32 + ll : 0][kc]));
+        d00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bl0, d00, 0, 0, 0);
+        d01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bl1, d01, 0, 0, 0);
+        d10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bl0, d10, 0, 0, 0);
+        d11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bl1, d11, 0, 0, 0);
+        d00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al0, bh0, d00, 0, 0, 0);
+        d01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al0, bh1, d01, 0, 0, 0);
+        d10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al1, bh0, d10, 0, 0, 0);
+        d11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al1, bh1, d11, 0, 0, 0);
+      }
+    }
+    if (kt + 1 < nk) BH_STORE(cur ^ 1);
+    __syncthreads();
+  }
+#undef BH_LOAD
+#undef BH_STORE
+  const int64_t row0 = m0 + wm + 4 * hl, col0 = n0 + wn + ll;
+  float* oc = part_c + ts * M_pad * C_pad;
+  float* orr = part_r + ts * M_pad * C_pad;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t row = row0 + 8 * (r >> 2) + (r & 3);
+    if (COARSE) {
+      oc[row * C_pad + col0] = c00[r];
+      oc[row * C_pad + col0 + 32] = c01[r];
+      oc[(row + 32) * C_pad + col0] = c10[r];
+      oc[(row + 32) * C_pad + col0 + 32] = c11[r];
+    }
+    if (CORR) {
+      orr[row * C_pad + col0] = d00[r];
+      orr[row * C_pad + col0 + 32] = d01[r];
+      orr[(row + 32) * C_pad + col0] = d10[r];
+      orr[(row + 32) * C_pad + col0 + 32] = d11[r];
+    }
+  }
+}
+
+// coeffs = sum_s (coarse + corr) (corr absent: coarse only); coarse_out = sum_s coarse.
+__global__ __launch_bounds__(256) void k_reduce2(const float* __restrict__ part_c,
+                                                 const float* __restrict__ part_r, int nsplit,
+                                                 int64_t M_pad, int64_t C_pad, int64_t B, int64_t C,
+                                                 const int32_t* __restrict__ csrc,
+                                                 const float* __restrict__ csgn,
+                                                 float* __restrict__ coeffs,
+                                                 float* __restrict__ coarse_out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * C) return;
+  const int64_t b = t / C, q = t % C;
+  const int32_t sr = csrc[2 * q], si = csrc[2 * q + 1];
+  float cre = 0.0f, cim = 0.0f, rre = 0.0f, rim = 0.0f;
+  for (int s = 0; s < nsplit; ++s) {
+    const int64_t o = (int64_t)s * M_pad * C_pad + b * C_pad;
+    cre += part_c[o + sr];
+    if (si >= 0) cim += part_c[o + si];
+    if (part_r) {
+      rre += part_r[o + sr];
+      if (si >= 0) rim += part_r[o + si];
+    }
+  }
+  const float gr = csgn[2 * q], gi = csgn[2 * q + 1];
+  coeffs[2 * t] = (cre + rre) * gr;
+  coeffs[2 * t + 1] = (si >= 0) ? (cim + rim) * gi : 0.0f;
+  if (coarse_out) {
+    coarse_out[2 * t] = cre * gr;
+    coarse_out[2 * t + 1] = (si >= 0) ? cim * gi : 0.0f;
+  }
+}
+
+}  // namespace
+
+int ensure_bf16_basis(bh_plan* p) {
+  if (p->psi_h) return BH_OK;
+  const size_t n = (size_t)p->C_pad * p->V_pad;
+  if (hipMalloc((void**)&p->psi_h, n * sizeof(uint16_t)) != hipSuccess ||
+      hipMalloc((void**)&p->psi_l, n * sizeof(uint16_t)) != hipSuccess) {
+    if (p->psi_h) (void)hipFree(p->psi_h);
+    p->psi_h = nullptr;
+    p->psi_l = nullptr;
+    (void)hipGetLastError();
+    return set_error(BH_ENOMEM, "BF16 basis allocation failed");
+  }
+  hipLaunchKernelGGL(k_psi_split, dim3((unsigned)(p->V_pad / 32), (unsigned)(p->C_pad / 32)),
+                     dim3(256), 0, 0, p->psi, p->V_pad, p->C_pad, p->psi_h, p->psi_l);
+  BH_HIP(hipGetLastError());
+  BH_HIP(hipDeviceSynchronize());
+  return BH_OK;
+}
+
+int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, float* coeffs,
+                       float* coarse_out, hipStream_t s) {
+  if (B == 0) return BH_OK;
+  int rc = ensure_bf16_basis(p);
+  if (rc != BH_OK) return rc;
+  const int64_t M_pad = ((B + BM - 1) / BM) * BM;
+  const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
+  const int64_t nk_total = p->V_pad / BK;   // multiple of 16
+  int nsplit = 1;
+  while (nsplit < 16 && mt * nt * nsplit < 1024 && (nk_total / (nsplit * 2)) >= 8) nsplit *= 2;
+  const int nk = (int)(nk_total / nsplit);
+  const size_t fbytes = (size_t)M_pad * p->V_pad * sizeof(uint16_t);
+  const size_t pbytes = (size_t)nsplit * M_pad * p->C_pad * sizeof(float);
+  if ((rc = grow(p->gathered, 2 * fbytes)) != BH_OK) return rc;
+  if ((rc = grow(p->partial, (refine ? 2 : 1) * pbytes)) != BH_OK) return rc;
+  uint16_t* fh = (uint16_t*)p->gathered.ptr;
+  uint16_t* fl = fh + (size_t)M_pad * p->V_pad;
+  float* part_c = (float*)p->partial.ptr;
+  float* part_r = refine ? part_c + (size_t)nsplit * M_pad * p->C_pad : nullptr;
+  const int64_t vol_stride = (int64_t)p->N * p->N * p->N;
+  {
+    ProfScope ps(p, "gather_bf16", s, B);
+    const unsigned gy = (unsigned)(M_pad < 4096 ? M_pad : 4096);
+    hipLaunchKernelGGL(k_gather_split, dim3((unsigned)((p->V_pad + 255) / 256), gy), dim3(256), 0,
+                       s, vols, vol_stride, B, p->vidx, p->V, p->V_pad, M_pad, fh, fl);
+  }
+  BH_HIP(hipGetLastError());
+  {
+    ProfScope ps(p, refine ? "gemm_bf16x3" : "gemm_bf16", s, B);
+    const dim3 grid((unsigned)(mt * nt * nsplit));
+    if (refine)
+      hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, dim3(256), 0, s, fh, fl, p->psi_h,
+                         p->psi_l, part_c, part_r, M_pad, p->C_pad, p->V_pad, nk, nsplit);
+    else
+      hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, dim3(256), 0, s, fh, fl, p->psi_h,
+                         p->psi_l, part_c, part_c, M_pad, p->C_pad, p->V_pad, nk, nsplit);
+  }
+  BH_HIP(hipGetLastError());
+  {
+    ProfScope ps(p, "reduce", s, B);
+    const int64_t tot = B * p->C;
+    hipLaunchKernelGGL(k_reduce2, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part_c,
+                       part_r, nsplit, M_pad, p->C_pad, B, p->C, p->csrc, p->csgn, coeffs,
+                       coarse_out);
+  }
+  BH_HIP(hipGetLastError());
+  return BH_OK;
+}
+
+}  // namespace bh

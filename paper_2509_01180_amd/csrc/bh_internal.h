@@ -79,6 +79,8 @@ struct bh_plan {
   int64_t V = 0, V_pad = 0;      // ball voxels, padded to kGemmKAlign
   int64_t C = 0, C_pad = 0;      // complex coefficients of L_max, padded to kGemmBN
   float* psi = nullptr;          // [V_pad][C_pad] h^3 * real columns of conj(psi)
+  uint16_t* psi_h = nullptr;     // [C_pad][V_pad] BF16 of psi (built on first BF16 use)
+  uint16_t* psi_l = nullptr;     // [C_pad][V_pad] BF16 of psi - psi_h
   int32_t* vidx = nullptr;       // [V] linear voxel index of each ball voxel
   int32_t* csrc = nullptr;       // [C][2] real column feeding re/im of each complex coefficient
   float* csgn = nullptr;         // [C][2] sign applied to it
@@ -112,6 +114,8 @@ int get_band(bh_plan* p, int L, const DevBand** out);
 // launchers (return BH_OK or an error code)
 int build_basis(bh_plan* p);
 int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s);
+int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, float* coeffs,
+                       float* coarse_out, hipStream_t s);
 int launch_cross_power_dense(bh_plan* p, const DevBand& band, const float* a, const float* b,
                              int64_t B, double* xi, hipStream_t s);
 int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const float* b, int64_t B,

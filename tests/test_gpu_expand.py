@@ -110,3 +110,40 @@ def test_expand_full_size_sampled():
     print("normwise", err)
     assert np.all(err <= TOL)
     assert np.all(np.isfinite(got))
+
+
+def test_expand_bf16_modes():
+    """BF16 expansion (basis and samples rounded to BF16, FP32 accumulation)
+    and its split-BF16 refinement against the FP64 oracle.  Bars: BF16 keeps
+    ~8 bits per term (2^-9 rounding of each factor), so <= 5e-3 normwise;
+    BF16X3 drops only lo*lo and the ~2^-17 split residuals: <= 1e-5."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd._lib import BhError
+    dev = cuda_device()
+    w = synth.CONFIG2
+    rng = np.random.default_rng(21)
+    B = 200
+    vols = (0.1 * rng.standard_normal((B, w.N, w.N, w.N))).astype(np.float32)
+    sample = [0, 7, 199]
+    for i in sample:
+        vols[i] = w.particle(i)
+    ref = expand.expand(vols[sample].astype(np.float64), basis.IndexSet(w.L_max))
+    say(f"expand bf16 modes N={w.N} L={w.L_max} B={B}")
+    plan = Plan(w.N, w.L_max, device=0)
+    dv = torch.from_numpy(vols).to(dev)
+    c1 = plan.expand_ex(dv, "bf16")
+    coarse = torch.empty_like(c1)
+    c3 = plan.expand_ex(dv, "bf16x3", coarse=coarse)
+    c32 = plan.expand_ex(dv, "fp32")
+    torch.cuda.synchronize()
+    e1 = normwise(to_complex(c1)[sample], ref)
+    e3 = normwise(to_complex(c3)[sample], ref)
+    e32 = normwise(to_complex(c32)[sample], ref)
+    print(f"normwise error: bf16 {e1}, bf16x3 {e3}, fp32 {e32}")
+    assert np.all(e1 <= 5e-3) and np.all(e1 >= 1e-5)     # genuinely BF16
+    assert np.all(e3 <= 1e-5)
+    np.testing.assert_allclose(coarse.cpu().numpy(), c1.cpu().numpy(), rtol=0, atol=1e-6 * float(c1.abs().max()))
+    with pytest.raises(BhError):
+        plan.expand_ex(dv, "bf16", coarse=coarse)
+    plan.close()
