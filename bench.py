@@ -41,7 +41,7 @@ PEAK_FP32_MFMA = 157.3e12      # MI355X dense FP32 matrix, FLOP/s
 PEAK_BF16_MFMA = 2.5e15        # MI355X dense BF16 matrix, FLOP/s
 PEAK_HBM = 8.0e12              # bytes/s
 
-# Operation counts of the score/gradient evaluation (see DESIGN.md):
+# Operation counts of the score/gradient evaluation:
 # per (class, l) entry of the recurrence: 8 FMA accumulations + 5 recurrence
 # operations (u, ap*sin(beta), two FMA for e, two for de/dbeta) = 25 flops;
 # per class: seeds, the two phase products, the four output updates and
@@ -102,7 +102,18 @@ def cpu_baseline(w: synth.Workload, n_particles: int):
     dt = time.perf_counter() - t0
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    return dt, cpu, np.array(out)
+    return dt, cpu, np.array(out), A
+
+
+def geodesic_deg(e1, e2):
+    """Angle (degrees) between the rotations of Euler triples [..., 3]."""
+    d = np.linalg.norm(synth.euler_zyz_to_matrix(e1) - synth.euler_zyz_to_matrix(e2), axis=(-2, -1))
+    return np.degrees(2 * np.arcsin(np.minimum(1.0, d / (2 * np.sqrt(2)))))
+
+
+def to_complex(t):
+    x = t.detach().cpu().numpy().astype(np.float64)
+    return x[..., 0] + 1j * x[..., 1]
 
 
 def main():
@@ -119,13 +130,28 @@ def main():
     ap.add_argument("--calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed "
                          "region (reference kernel for hardware traffic counters)")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the serving loop on a Poisson request stream instead")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: requests per second")
+    ap.add_argument("--duration", type=float, default=30.0, help="serving: seconds of arrivals")
+    ap.add_argument("--boxes", default="32,64,96", help="serving: box edges served")
+    ap.add_argument("--budget-gib", type=float, default=24.0,
+                    help="serving: device memory for in-flight particles")
+    ap.add_argument("--max-cohort", type=int, default=2048,
+                    help="serving: particles admitted per box edge per tick")
+    ap.add_argument("--pool", type=int, default=16,
+                    help="serving: pre-rendered particles per (box, template)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(particles shard across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path here "
+              "(particles would shard across GPUs with no exchange).", file=sys.stderr)
         sys.exit(2)
+
+    if args.serving:
+        serve_bench(args)
+        return
 
     import torch
     from paper_2509_01180_amd.api import Plan
@@ -260,11 +286,25 @@ def main():
         "setup": {"input_generation_s": round(t_gen, 1), "plan_build_s": round(t_plan, 2)},
     }
 
+    if args.precision == "bf16x3":
+        # the plain path on the same inputs (untimed), for the comparison
+        a_plain = plan.expand(vols)
+        eu_plain, _sc = plan.align(a_plain, b, w.bands, starts, w.steps)
+        torch.cuda.synchronize()
+        dp = geodesic_deg(eu_h, eu_plain.cpu().numpy())
+        result["accuracy"]["median_deg_vs_plain_path"] = round(float(np.median(dp)), 4)
+        result["accuracy"]["p99_deg_vs_plain_path"] = round(float(np.percentile(dp, 99)), 4)
+        result["accuracy"]["frac_within_0.5deg_of_plain"] = round(float(np.mean(dp <= 0.5)), 4)
+
     if args.cpu_sample > 0:
-        dt, cpu, e_oracle = cpu_baseline(w, args.cpu_sample)
-        Ro = synth.euler_zyz_to_matrix(e_oracle)
-        dd = np.linalg.norm(Ro - R_est[:args.cpu_sample], axis=(1, 2))
-        ang_o = np.degrees(2 * np.arcsin(np.minimum(1.0, dd / (2 * np.sqrt(2)))))
+        dt, cpu, e_oracle, A_oracle = cpu_baseline(w, args.cpu_sample)
+        ang_o = geodesic_deg(e_oracle, eu_h[:args.cpu_sample])
+        n_s = args.cpu_sample
+        ref_norm = np.linalg.norm(A_oracle, axis=1)
+        coeff_err = {"final": np.linalg.norm(to_complex(a[:n_s]) - A_oracle, axis=1) / ref_norm}
+        if a_coarse is not None:
+            coeff_err["coarse_bf16"] = np.linalg.norm(to_complex(a_coarse[:n_s]) - A_oracle, axis=1) / ref_norm
+        result["accuracy"]["coeff_rel_err_vs_oracle"] = {k: float(v.max()) for k, v in coeff_err.items()}
         result["cpu_baseline"] = {
             "value": round(args.cpu_sample / dt, 5),
             "unit": "subtomograms/s",
@@ -276,6 +316,190 @@ def main():
         }
         result["accuracy"]["max_deg_vs_oracle_on_sample"] = round(float(ang_o.max()), 4)
     plan.close()
+    print(json.dumps(result), flush=True)
+
+
+# ------------------------------------------------------------------ serving --
+
+SERVE_PLANS = {32: (16, (8, 16)), 48: (24, (8, 16, 24)), 64: (32, (8, 16, 24, 32)),
+               96: (40, (8, 16, 24, 32, 40))}
+
+
+def serve_bench(args):
+    """Serving loop on a Poisson stream of requests (mixed box edges, 8
+    resident templates).  Prints one JSON line: offered and sustained
+    throughput, latency percentiles, accuracy against the planted rotations,
+    and the plain batch path's throughput at 64^3 for comparison."""
+    import torch
+    import synth.serving as ss
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd.serving import Engine, Request, latency_summary
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    boxes = [int(x) for x in args.boxes.split(",")]
+    P, T = 64, 20
+    blobs = ss.serving_templates()
+    nt = len(blobs)
+    t_gen = time.perf_counter()
+    pools, truth = {}, {}
+    with ThreadPoolExecutor(max(1, args.threads)) as ex:
+        for N in boxes:
+            jobs = [(t, j) for t in range(nt) for j in range(args.pool)]
+            vols = list(ex.map(lambda tj: ss.pool_particle(blobs[tj[0]], N, tj[0], tj[1]), jobs))
+            pools[N] = torch.from_numpy(np.stack(vols)).to(dev)
+            truth[N] = np.stack([ss.pool_rotation(N, t, j) for t, j in jobs])
+            del vols
+            print(f"# pool of {len(jobs)} particles at {N}^3 ready", file=sys.stderr, flush=True)
+    start_pool = torch.from_numpy(ss.start_pool(4096, P)).to(dev)
+    t_gen = time.perf_counter() - t_gen
+
+    t_plan = time.perf_counter()
+    plans, tmpls = {}, {}
+    for N in boxes:
+        L, _bands = SERVE_PLANS[N]
+        plans[N] = Plan(N, L, device=0)
+        tv = np.stack([synth.render_blobs(b, N) for b in blobs]).astype(np.float32)
+        tmpls[N] = plans[N].expand(torch.from_numpy(tv).to(dev))
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t_plan
+    print(f"# plans built in {t_plan:.1f} s", file=sys.stderr, flush=True)
+
+    eng = Engine({N: SERVE_PLANS[N] for N in boxes}, tmpls, restarts=P, steps=T,
+                 budget_bytes=int(args.budget_gib * (1 << 30)), max_cohort=args.max_cohort,
+                 plans=plans)
+
+    def make_request(spec, arrival=None):
+        # the index tensors are made inside the callables, which the engine
+        # calls on the stream that consumes them
+        N, t, n = spec.box, spec.template, spec.n
+
+        def volumes():
+            j = (spec.offset + torch.arange(n, device=dev)) % args.pool + t * args.pool
+            return pools[N].index_select(0, j)
+
+        def starts():
+            k = (spec.start_offset + torch.arange(n, device=dev)) % start_pool.shape[0]
+            return start_pool.index_select(0, k)
+
+        return Request(box=N, template=t, n=n, rid=spec.rid, arrival=arrival,
+                       volumes=volumes, starts=starts)
+
+    # warm-up: one request per box edge through the whole loop (builds the
+    # BF16 bases and band tables before the clock starts)
+    for i, N in enumerate(boxes):
+        eng.submit(make_request(ss.RequestSpec(-1 - i, 0.0, N, 0, 4, 0, 0)))
+    eng.drain()
+
+    reqs = ss.request_stream(args.rate, args.duration, boxes, seed=0, pool=args.pool)
+    print(f"# {len(reqs)} requests, {sum(r.n for r in reqs)} particles over {args.duration} s "
+          f"at {args.rate}/s", file=sys.stderr, flush=True)
+    done = []
+    submitted = []
+    i = 0
+    t0 = time.perf_counter()
+    last_note = t0
+    ticks = 0
+    while True:
+        now = time.perf_counter() - t0
+        if now >= args.duration:
+            break
+        while i < len(reqs) and reqs[i].arrival <= now:
+            submitted.append(eng.submit(make_request(reqs[i], t0 + reqs[i].arrival)))
+            i += 1
+        if not eng.busy():
+            nxt = reqs[i].arrival if i < len(reqs) else args.duration
+            time.sleep(max(0.0, min(nxt - now, 0.01)))
+            continue
+        done += eng.step()
+        ticks += 1
+        if time.perf_counter() - last_note > 10:
+            last_note = time.perf_counter()
+            print(f"# t={now:.0f}s ticks={ticks} done={sum(r.n for r in done)} particles, "
+                  f"queued={eng.sched.queued_particles()}", file=sys.stderr, flush=True)
+    t_end = time.perf_counter()
+    backlog_queued = eng.sched.queued_particles()
+    backlog_live = sum(c.n for c in eng.sched.live)
+    # finish what is on the device (not counted below), then stop
+    eng.sched.queue.clear()
+    done += eng.drain()
+
+    warm = min(5.0, 0.2 * args.duration)
+    win = [r for r in done if r.done is not None and t0 + warm <= r.done <= t_end]
+    span = (t_end - t0) - warm
+    sustained = sum(r.n for r in win) / span
+    offered = sum(r.n for r in reqs) / args.duration
+    lat_all = latency_summary([r for r in done if r.arrival >= t0 + warm and r.done <= t_end])
+
+    per_box = {}
+    for N in boxes:
+        rs = [r for r in win if r.box == N]
+        ang = []
+        for r in done:
+            if r.box != N or r.euler is None or r.rid < 0:
+                continue
+            sp = reqs[r.rid]
+            jj = (sp.offset + np.arange(r.n)) % args.pool + sp.template * args.pool
+            R_est = synth.euler_zyz_to_matrix(r.euler)
+            d = np.linalg.norm(R_est - np.transpose(truth[N][jj], (0, 2, 1)), axis=(1, 2))
+            ang.append(np.degrees(2 * np.arcsin(np.minimum(1.0, d / (2 * np.sqrt(2))))))
+        ang = np.concatenate(ang) if ang else np.zeros(0)
+        per_box[str(N)] = {
+            "L_max": SERVE_PLANS[N][0], "bands": list(SERVE_PLANS[N][1]),
+            "offered_per_s": round(sum(r.n for r in reqs if r.box == N) / args.duration, 1),
+            "sustained_per_s": round(sum(r.n for r in rs) / span, 1),
+            "latency": latency_summary([r for r in rs if r.arrival >= t0 + warm]),
+            "median_deg_vs_planted": round(float(np.median(ang)), 3) if ang.size else None,
+            "p90_deg_vs_planted": round(float(np.percentile(ang, 90)), 3) if ang.size else None,
+        }
+
+    plain = None
+    if 64 in boxes:
+        # the plain batch path (FP32 expansion, one template, 1000 particles
+        # per call) on the same particles, for the served-vs-plain comparison
+        plan = plans[64]
+        L, bands = SERVE_PLANS[64]
+        jj = torch.arange(1000, device=dev) % (nt * args.pool)
+        vols = pools[64].index_select(0, jj)
+        st = start_pool[:1000].contiguous()
+        b = tmpls[64][0].contiguous()
+        a = torch.empty((1000, plan.C, 2), dtype=torch.float32, device=dev)
+        plan.expand(vols, out=a)
+        plan.align(a, b, bands, st, T)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for _ in range(3):
+            plan.expand(vols, out=a)
+            plan.align(a, b, bands, st, T)
+        torch.cuda.synchronize()
+        plain = 3000 / (time.perf_counter() - tp)
+        del vols, a
+
+    result = {
+        "metric": "served subtomograms/s (Poisson arrivals, mixed box edges, 8 templates)",
+        "value": round(sustained, 1),
+        "unit": "subtomograms/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "offered_per_s": round(offered, 1),
+        "backlog_at_end": {"queued_particles": backlog_queued, "in_flight_particles": backlog_live},
+        "latency": lat_all,
+        "per_box": per_box,
+        "plain_path_64_per_s": round(plain, 1) if plain else None,
+        "ticks": ticks,
+        "dtype": "bf16x3 expansion (bf16 coarse bands, refined final band)/f64 score",
+        "data": "synthetic",
+        "config": {
+            "workload": f"Poisson {args.rate}/s requests of U{{1..512}} subtomograms, boxes {boxes}, "
+                        f"8 resident templates (30-80 blobs), +/-60 deg wedge, SNR 0.05, "
+                        f"64 restarts, 20 steps/band",
+            "duration_s": args.duration, "warmup_excluded_s": warm,
+            "budget_gib": args.budget_gib, "max_cohort": args.max_cohort,
+            "parallelism": "single GPU",
+        },
+        "setup": {"pool_generation_s": round(t_gen, 1), "plan_build_s": round(t_plan, 1)},
+    }
+    eng.close()
     print(json.dumps(result), flush=True)
 
 

@@ -126,8 +126,13 @@ int bh_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, void* str
  *                    not NULL (dev float[B][C(L_max)][2]) the hi*hi part
  *                    alone (the BF16 result) is written there as well.
  * The BF16 basis (2 bytes x V x C for hi and again for lo) is built on the
- * first BF16 call and kept by the plan. */
-enum { BH_EXPAND_FP32 = 0, BH_EXPAND_BF16 = 1, BH_EXPAND_BF16X3 = 2 };
+ * first BF16 call and kept by the plan.
+ * Adding BH_EXPAND_BATCH_INVARIANT to the mode fixes the summation order of
+ * each particle's coefficients independently of B (a particle expanded
+ * alone or in any batch gives the same bits); otherwise small batches split
+ * the voxel sum further to fill the GPU. */
+enum { BH_EXPAND_FP32 = 0, BH_EXPAND_BF16 = 1, BH_EXPAND_BF16X3 = 2,
+       BH_EXPAND_BATCH_INVARIANT = 16 };
 int bh_expand_ex(bh_plan* p, const float* vols, int64_t B, int mode, float* coeffs, float* coarse,
                  void* stream);
 
@@ -177,12 +182,28 @@ typedef struct {
   double step_init;         /* > 0                                        */
   double step_grow;         /* > 0                                        */
   double step_shrink;       /* > 0                                        */
+  int32_t batch_invariant;  /* nonzero: a particle's results do not depend
+                               on the other particles of the call (fixed
+                               work split); 0: the split may widen for
+                               small batches (lower latency, summation
+                               order then depends on the batch size)      */
 } bh_align_opts;
 
 int bh_align(bh_plan* p, const float* a, const float* b, int64_t B,
              const bh_align_opts* opts, const double* starts,
              double* euler_out, double* score_out,
              double* all_euler, double* all_score, void* stream);
+
+/* As bh_align, against one of several templates per particle:
+ * templates: dev float[n_templates][C(L_max)][2]
+ * tmpl_idx:  dev int32[B], template of each particle (values outside
+ *            0..n_templates-1 are clamped); may be NULL if n_templates == 1.
+ * A call with one band and all_euler set advances every restart by one band
+ * of the march; its all_euler output is the next call's starts. */
+int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templates,
+               const int32_t* tmpl_idx, int64_t B, const bh_align_opts* opts,
+               const double* starts, double* euler_out, double* score_out,
+               double* all_euler, double* all_score, void* stream);
 
 /* ---------------------------------------------------------------------
  * Per-kernel timing (for measurement; off by default).

@@ -16,6 +16,7 @@ LIB_PATH = os.environ.get("BH_LIBRARY") or os.path.join(_PKG, "libbh.so")
 
 BH_OK, BH_EINVAL, BH_ENOMEM, BH_EDEVICE, BH_EUNSUPPORTED = 0, -1, -2, -3, -4
 BH_EXPAND_FP32, BH_EXPAND_BF16, BH_EXPAND_BF16X3 = 0, 1, 2
+BH_EXPAND_BATCH_INVARIANT = 16
 BH_MAX_L = 64
 BH_MAX_N = 256
 
@@ -35,6 +36,7 @@ class AlignOpts(ctypes.Structure):
         ("step_init", ctypes.c_double),
         ("step_grow", ctypes.c_double),
         ("step_shrink", ctypes.c_double),
+        ("batch_invariant", ctypes.c_int32),
     ]
 
 
@@ -60,6 +62,7 @@ SIGNATURES = {
     "bh_cross_power": (_I, [_P, _P, _P, _I64, _I, _P, _P]),
     "bh_correlate": (_I, [_P, _P, _P, _I64, _I, _P, _I, _P, _P, _P]),
     "bh_align": (_I, [_P, _P, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),
+    "bh_align_t": (_I, [_P, _P, _P, _I, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),
     "bh_profile_enable": (_I, [_P, _I]),
     "bh_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(_I64)]),

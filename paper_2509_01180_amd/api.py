@@ -13,7 +13,7 @@ from typing import Sequence
 import numpy as np
 import torch
 
-from ._lib import AlignOpts, check, lib
+from ._lib import BH_EXPAND_BATCH_INVARIANT, AlignOpts, check, lib
 
 __all__ = ["Plan", "index_size", "index_table", "radial_table", "ball_voxels",
            "dense_xi_size"]
@@ -95,6 +95,7 @@ class Plan:
               "bh_plan_create")
         self._h = h
         self.C = self.num_coeffs(self.L_max)
+        self.V = ball_voxels(self.N)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -137,13 +138,16 @@ class Plan:
         return out
 
     def expand_ex(self, vols: torch.Tensor, mode: str = "fp32", out: torch.Tensor | None = None,
-                  coarse: torch.Tensor | None = None) -> torch.Tensor:
+                  coarse: torch.Tensor | None = None,
+                  batch_invariant: bool = False) -> torch.Tensor:
         """Expansion in mode "fp32", "bf16" or "bf16x3" (see bh_expand_ex).
 
         With mode "bf16x3" and a `coarse` tensor [B, C, 2], the BF16 (hi*hi)
-        result is written there too.
+        result is written there too.  With batch_invariant, each particle's
+        coefficients are the same bits whatever batch it is expanded in.
         """
         modes = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+        code = modes[mode] | (BH_EXPAND_BATCH_INVARIANT if batch_invariant else 0)
         B = vols.shape[0]
         _dev(vols, torch.float32, (B, self.N, self.N, self.N), "vols")
         if out is None:
@@ -151,7 +155,7 @@ class Plan:
         _dev(out, torch.float32, (B, self.C, 2), "out")
         if coarse is not None:
             _dev(coarse, torch.float32, (B, self.C, 2), "coarse")
-        check(lib().bh_expand_ex(self._h, _ptr(vols), B, modes[mode], _ptr(out), _ptr(coarse),
+        check(lib().bh_expand_ex(self._h, _ptr(vols), B, code, _ptr(out), _ptr(coarse),
                                  _stream()), "bh_expand_ex")
         return out
 
@@ -181,11 +185,13 @@ class Plan:
 
     def align(self, a: torch.Tensor, b: torch.Tensor, bands: Sequence[int], starts: torch.Tensor,
               steps: int, step_init: float = 1.0, step_grow: float = 1.25,
-              step_shrink: float = 0.5, return_all: bool = False):
+              step_shrink: float = 0.5, return_all: bool = False,
+              batch_invariant: bool = False):
         """Best rotation per particle: (euler [B, 3], score [B]) float64.
 
         With return_all, also the final point [B, P, 3] and score [B, P] of
-        every restart.
+        every restart.  With batch_invariant, each particle's result is
+        independent of the batch it is aligned in.
         """
         B = a.shape[0]
         P = starts.shape[1]
@@ -194,13 +200,55 @@ class Plan:
         _dev(starts, torch.float64, (B, P, 3), "starts")
         bl = (ctypes.c_int32 * len(bands))(*[int(x) for x in bands])
         o = AlignOpts(ctypes.cast(bl, ctypes.POINTER(ctypes.c_int32)), len(bands), int(steps), P,
-                      float(step_init), float(step_grow), float(step_shrink))
+                      float(step_init), float(step_grow), float(step_shrink),
+                      int(bool(batch_invariant)))
         eu = torch.empty((B, 3), dtype=torch.float64, device=a.device)
         sc = torch.empty((B,), dtype=torch.float64, device=a.device)
         ae = torch.empty((B, P, 3), dtype=torch.float64, device=a.device) if return_all else None
         asc = torch.empty((B, P), dtype=torch.float64, device=a.device) if return_all else None
         check(lib().bh_align(self._h, _ptr(a), _ptr(b), B, ctypes.byref(o), _ptr(starts),
                              _ptr(eu), _ptr(sc), _ptr(ae), _ptr(asc), _stream()), "bh_align")
+        if return_all:
+            return eu, sc, ae, asc
+        return eu, sc
+
+    def align_t(self, a: torch.Tensor, templates: torch.Tensor, tmpl_idx: torch.Tensor | None,
+                bands: Sequence[int], starts: torch.Tensor, steps: int, step_init: float = 1.0,
+                step_grow: float = 1.25, step_shrink: float = 0.5, return_all: bool = False,
+                out: tuple | None = None, batch_invariant: bool = False):
+        """As align, with particle i matched against templates[tmpl_idx[i]].
+
+        templates: [T, C, 2] float32; tmpl_idx: [B] int32 (None if T == 1).
+        out: optional (euler, score, all_euler, all_score) buffers to fill.
+        """
+        B = a.shape[0]
+        P = starts.shape[1]
+        T = templates.shape[0]
+        _dev(a, torch.float32, (B, self.C, 2), "a")
+        _dev(templates, torch.float32, (T, self.C, 2), "templates")
+        _dev(starts, torch.float64, (B, P, 3), "starts")
+        if tmpl_idx is not None:
+            _dev(tmpl_idx, torch.int32, (B,), "tmpl_idx")
+        bl = (ctypes.c_int32 * len(bands))(*[int(x) for x in bands])
+        o = AlignOpts(ctypes.cast(bl, ctypes.POINTER(ctypes.c_int32)), len(bands), int(steps), P,
+                      float(step_init), float(step_grow), float(step_shrink),
+                      int(bool(batch_invariant)))
+        if out is None:
+            eu = torch.empty((B, 3), dtype=torch.float64, device=a.device)
+            sc = torch.empty((B,), dtype=torch.float64, device=a.device)
+            ae = torch.empty((B, P, 3), dtype=torch.float64, device=a.device) if return_all else None
+            asc = torch.empty((B, P), dtype=torch.float64, device=a.device) if return_all else None
+        else:
+            eu, sc, ae, asc = out
+            _dev(eu, torch.float64, (B, 3), "euler_out")
+            _dev(sc, torch.float64, (B,), "score_out")
+            if ae is not None:
+                _dev(ae, torch.float64, (B, P, 3), "all_euler")
+            if asc is not None:
+                _dev(asc, torch.float64, (B, P), "all_score")
+        check(lib().bh_align_t(self._h, _ptr(a), _ptr(templates), T, _ptr(tmpl_idx), B,
+                               ctypes.byref(o), _ptr(starts), _ptr(eu), _ptr(sc), _ptr(ae),
+                               _ptr(asc), _stream()), "bh_align_t")
         if return_all:
             return eu, sc, ae, asc
         return eu, sc

@@ -321,6 +321,8 @@ int bh_expand_ex(bh_plan* p, const float* vols, int64_t B, int mode, float* coef
                  void* stream) {
   if (!p) return set_error(BH_EINVAL, "plan is NULL");
   if (B < 0 || B > (1LL << 21)) return set_error(BH_EINVAL, "batch size out of range");
+  const bool invariant = (mode & BH_EXPAND_BATCH_INVARIANT) != 0;
+  mode &= ~BH_EXPAND_BATCH_INVARIANT;
   if (mode != BH_EXPAND_FP32 && mode != BH_EXPAND_BF16 && mode != BH_EXPAND_BF16X3)
     return set_error(BH_EINVAL, "unknown expansion mode");
   if (coarse && mode != BH_EXPAND_BF16X3)
@@ -330,9 +332,10 @@ int bh_expand_ex(bh_plan* p, const float* vols, int64_t B, int mode, float* coef
   return guarded([&]() -> int {
     DeviceGuard g(p->device);
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
-    if (mode == BH_EXPAND_FP32) return launch_expand(p, vols, B, coeffs, (hipStream_t)stream);
+    if (mode == BH_EXPAND_FP32)
+      return launch_expand(p, vols, B, coeffs, (hipStream_t)stream, invariant);
     return launch_expand_bf16(p, vols, B, mode == BH_EXPAND_BF16X3, coeffs, coarse,
-                              (hipStream_t)stream);
+                              (hipStream_t)stream, invariant);
   });
 }
 
@@ -371,12 +374,15 @@ int bh_correlate(bh_plan* p, const float* a, const float* b, int64_t B, int L, c
   });
 }
 
-int bh_align(bh_plan* p, const float* a, const float* b, int64_t B, const bh_align_opts* o,
-             const double* starts, double* euler_out, double* score_out, double* all_euler,
-             double* all_score, void* stream) {
+int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templates,
+               const int32_t* tmpl_idx, int64_t B, const bh_align_opts* o, const double* starts,
+               double* euler_out, double* score_out, double* all_euler, double* all_score,
+               void* stream) {
   if (!p) return set_error(BH_EINVAL, "plan is NULL");
   if (!o) return set_error(BH_EINVAL, "opts is NULL");
   if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
+  if (n_templates < 1 || n_templates > (1 << 20)) return set_error(BH_EINVAL, "bad template count");
+  if (n_templates > 1 && !tmpl_idx) return set_error(BH_EINVAL, "template index table is NULL");
   if (o->n_bands < 1 || o->n_bands > 16 || !o->bands) return set_error(BH_EINVAL, "bad band list");
   for (int i = 0; i < o->n_bands; ++i)
     if (o->bands[i] < 0 || o->bands[i] > p->L_max) return set_error(BH_EINVAL, "band outside 0..L_max");
@@ -385,13 +391,20 @@ int bh_align(bh_plan* p, const float* a, const float* b, int64_t B, const bh_ali
   if (!(o->step_init > 0) || !(o->step_grow > 0) || !(o->step_shrink > 0))
     return set_error(BH_EINVAL, "step parameters must be positive");
   if (B == 0) return BH_OK;
-  if (!a || !b || !starts || !euler_out || !score_out) return set_error(BH_EINVAL, "NULL buffer");
+  if (!a || !templates || !starts || !euler_out || !score_out) return set_error(BH_EINVAL, "NULL buffer");
   return guarded([&]() -> int {
     DeviceGuard g(p->device);
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
-    return launch_align(p, a, b, B, *o, starts, euler_out, score_out, all_euler, all_score,
-                        (hipStream_t)stream);
+    return launch_align(p, a, templates, n_templates > 1 ? tmpl_idx : nullptr, n_templates, B, *o,
+                        starts, euler_out, score_out, all_euler, all_score, (hipStream_t)stream);
   });
+}
+
+int bh_align(bh_plan* p, const float* a, const float* b, int64_t B, const bh_align_opts* o,
+             const double* starts, double* euler_out, double* score_out, double* all_euler,
+             double* all_score, void* stream) {
+  return bh_align_t(p, a, b, 1, nullptr, B, o, starts, euler_out, score_out, all_euler, all_score,
+                    stream);
 }
 
 }  // extern "C"

@@ -165,13 +165,13 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ part, 
 
 }  // namespace
 
-int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s) {
+int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s,
+                  bool batch_invariant) {
   if (B == 0) return BH_OK;
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
   const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
   const int64_t nk_total = p->V_pad / BK;           // multiple of 16
-  int nsplit = 1;
-  while (nsplit < 16 && mt * nt * nsplit < 1024 && (nk_total / (nsplit * 2)) >= 8) nsplit *= 2;
+  const int nsplit = expand_split(mt, nt, nk_total, batch_invariant);
   const int nk = (int)(nk_total / nsplit);
   int rc;
   if ((rc = grow(p->gathered, (size_t)p->V_pad * M_pad * sizeof(float))) != BH_OK) return rc;

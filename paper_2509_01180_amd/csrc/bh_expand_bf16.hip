@@ -262,15 +262,14 @@ int ensure_bf16_basis(bh_plan* p) {
 }
 
 int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, float* coeffs,
-                       float* coarse_out, hipStream_t s) {
+                       float* coarse_out, hipStream_t s, bool batch_invariant) {
   if (B == 0) return BH_OK;
   int rc = ensure_bf16_basis(p);
   if (rc != BH_OK) return rc;
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
   const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
   const int64_t nk_total = p->V_pad / BK;   // multiple of 16
-  int nsplit = 1;
-  while (nsplit < 16 && mt * nt * nsplit < 1024 && (nk_total / (nsplit * 2)) >= 8) nsplit *= 2;
+  const int nsplit = expand_split(mt, nt, nk_total, batch_invariant);
   const int nk = (int)(nk_total / nsplit);
   const size_t fbytes = (size_t)M_pad * p->V_pad * sizeof(uint16_t);
   const size_t pbytes = (size_t)nsplit * M_pad * p->C_pad * sizeof(float);

@@ -113,14 +113,26 @@ int get_band(bh_plan* p, int L, const DevBand** out);
 
 // launchers (return BH_OK or an error code)
 int build_basis(bh_plan* p);
-int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s);
+// Split-K factor of the expansion GEMM: doubled while the grid has fewer
+// than 1024 tiles and each split keeps at least 8 K-steps.  With
+// batch_invariant the particle-tile count is taken as 8 (1024 particles)
+// whatever the batch, so a particle's sums never depend on the batch size.
+inline int expand_split(int64_t mt, int64_t nt, int64_t nk_total, bool batch_invariant) {
+  if (batch_invariant) mt = 8;
+  int nsplit = 1;
+  while (nsplit < 16 && mt * nt * nsplit < 1024 && (nk_total / (nsplit * 2)) >= 8) nsplit *= 2;
+  return nsplit;
+}
+int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s,
+                  bool batch_invariant = false);
 int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, float* coeffs,
-                       float* coarse_out, hipStream_t s);
+                       float* coarse_out, hipStream_t s, bool batch_invariant = false);
 int launch_cross_power_dense(bh_plan* p, const DevBand& band, const float* a, const float* b,
                              int64_t B, double* xi, hipStream_t s);
 int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const float* b, int64_t B,
                      const double* euler, int R, double* score, double* grad, hipStream_t s);
-int launch_align(bh_plan* p, const float* a, const float* b, int64_t B, const bh_align_opts& o,
+int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl, int n_tmpl,
+                 int64_t B, const bh_align_opts& o,
                  const double* starts, double* euler_out, double* score_out, double* all_euler,
                  double* all_score, hipStream_t s);
 

@@ -79,8 +79,16 @@ __global__ void k_xi_dense(const float* __restrict__ a, const float* __restrict_
   xi[(pb * E + t) * 2 + 1] = sim;
 }
 
+// Template of particle pb: tmpl[pb] clamped to [0, n_tmpl) (template 0 without a table).
+__device__ inline int64_t template_of(const int32_t* __restrict__ tmpl, int n_tmpl, int64_t pb) {
+  if (!tmpl) return 0;
+  const int t = tmpl[pb];
+  return t < 0 ? 0 : (t >= n_tmpl ? n_tmpl - 1 : t);
+}
+
 // Class-major weighted cross-power of one band: X[pb][e] = {X1re, X1im, X2re, X2im}.
-__global__ void k_xi_classes(const float* __restrict__ a, const float* __restrict__ b, int64_t C,
+__global__ void k_xi_classes(const float* __restrict__ a, const float* __restrict__ btab, int64_t C,
+                             const int32_t* __restrict__ tmpl, int n_tmpl,
                              int64_t n_entries, const int32_t* __restrict__ sel,
                              const double* __restrict__ wt, const int32_t* __restrict__ deg_start,
                              const int32_t* __restrict__ deg_off, double* __restrict__ X) {
@@ -90,6 +98,7 @@ __global__ void k_xi_classes(const float* __restrict__ a, const float* __restric
   const int l = sel[4 * e], m = sel[4 * e + 1], n = sel[4 * e + 2];
   const double w1 = wt[2 * e], w2 = wt[2 * e + 1];
   const float* ap = a + pb * 2 * C;
+  const float* b = btab + template_of(tmpl, n_tmpl, pb) * 2 * C;
   double x1r = 0, x1i = 0, x2r = 0, x2i = 0;
   for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
     const int o = deg_off[i];
@@ -110,12 +119,14 @@ __global__ void k_xi_classes(const float* __restrict__ a, const float* __restric
 }
 
 // W_b = sum_l l(l+1) ||a_l|| ||b_l|| over the band; one block per particle.
-__global__ void k_band_weight(const float* __restrict__ a, const float* __restrict__ b, int64_t C,
+__global__ void k_band_weight(const float* __restrict__ a, const float* __restrict__ btab, int64_t C,
+                              const int32_t* __restrict__ tmpl, int n_tmpl,
                               int L, const int32_t* __restrict__ deg_start,
                               const int32_t* __restrict__ deg_off, double* __restrict__ Wb) {
   __shared__ double part[BH_MAX_L + 1];
   const int64_t pb = blockIdx.x;
   const float* ap = a + pb * 2 * C;
+  const float* b = btab + template_of(tmpl, n_tmpl, pb) * 2 * C;
   for (int l = threadIdx.x; l <= L; l += blockDim.x) {
     double na = 0.0, nb = 0.0;
     for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
@@ -333,14 +344,15 @@ __global__ __launch_bounds__(64) void k_select(const double* __restrict__ state,
   }
 }
 
-int pick_waves(int64_t groups, int L) {
+int pick_waves(int64_t groups, int L, bool batch_invariant = false) {
   if (BH_SCORE_FIXED_W > 0) return BH_SCORE_FIXED_W;
   // Measured on MI355X (1000 particles x 64 restarts, bands 8..32): 12 waves
   // per workgroup at 6 waves per SIMD (two workgroups per CU) is fastest for
   // L > 8, 4 waves for L <= 8; small batches spread one particle over 16
-  // waves.  More than 2L+1 waves would have no p-group to work on.
+  // waves unless the split must not depend on the batch.  More than 2L+1
+  // waves would have no p-group to work on.
   int W = (L <= 8) ? 4 : 12;
-  if (groups < 256) W = 16;
+  if (groups < 256 && !batch_invariant) W = 16;
   while (W > 2 * L + 1 && W > 4) W = (W == 16) ? 12 : (W == 12 ? 8 : (W == 8 ? 6 : W - 1));
   return W;
 }
@@ -367,15 +379,15 @@ void launch_march_w(bh_plan* p, dim3 grid, hipStream_t s, const DevBand& band, c
                      o.step_shrink, state, sscore);
 }
 
-int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b, int64_t B,
-                 double** X, hipStream_t s) {
+int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b,
+                 const int32_t* tmpl, int n_tmpl, int64_t B, double** X, hipStream_t s) {
   // + kTablePad entries: the score loop reads up to three entries ahead
   int rc = grow(p->xi_scr, ((size_t)B * band.n_entries + kTablePad) * 4 * sizeof(double));
   if (rc != BH_OK) return rc;
   *X = (double*)p->xi_scr.ptr;
   ProfScope ps(p, "xi_classes", s, B);
   hipLaunchKernelGGL(k_xi_classes, dim3((unsigned)((band.n_entries + 127) / 128), (unsigned)B),
-                     dim3(128), 0, s, a, b, p->C, band.n_entries, band.sel, band.wt,
+                     dim3(128), 0, s, a, b, p->C, tmpl, n_tmpl, band.n_entries, band.sel, band.wt,
                      band.deg_start, band.deg_off, *X);
   BH_HIP(hipGetLastError());
   return BH_OK;
@@ -397,7 +409,7 @@ int launch_cross_power_dense(bh_plan* p, const DevBand& band, const float* a, co
 int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const float* b, int64_t B,
                      const double* euler, int R, double* score, double* grad, hipStream_t s) {
   double* X = nullptr;
-  int rc = prepare_band(p, band, a, b, B, &X, s);
+  int rc = prepare_band(p, band, a, b, nullptr, 1, B, &X, s);
   if (rc != BH_OK) return rc;
   const int64_t chunks = (R + 63) / 64;
   const dim3 grid((unsigned)chunks, (unsigned)B);
@@ -415,7 +427,8 @@ int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const floa
   return BH_OK;
 }
 
-int launch_align(bh_plan* p, const float* a, const float* b, int64_t B, const bh_align_opts& o,
+int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl, int n_tmpl,
+                 int64_t B, const bh_align_opts& o,
                  const double* starts, double* euler_out, double* score_out, double* all_euler,
                  double* all_score, hipStream_t s) {
   const int P = o.n_restarts;
@@ -438,14 +451,15 @@ int launch_align(bh_plan* p, const float* a, const float* b, int64_t B, const bh
   const dim3 grid((unsigned)chunks, (unsigned)B);
   for (const DevBand* band : bands) {
     double* X = nullptr;
-    if ((rc = prepare_band(p, *band, a, b, B, &X, s)) != BH_OK) return rc;
+    if ((rc = prepare_band(p, *band, a, b, tmpl, n_tmpl, B, &X, s)) != BH_OK) return rc;
     {
       ProfScope ps(p, "band_weight", s, B);
-      hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, b, p->C, band->L,
+      hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, b, p->C, tmpl,
+                         n_tmpl, band->L,
                          band->deg_start, band->deg_off, Wb);
     }
     BH_HIP(hipGetLastError());
-    const int W = pick_waves(chunks * B, band->L);
+    const int W = pick_waves(chunks * B, band->L, o.batch_invariant != 0);
     switch (W) {
       case 16: launch_march_w<16>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
       case 12: launch_march_w<12>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;

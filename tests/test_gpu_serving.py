@@ -1,0 +1,176 @@
+"""Serving path on the GPU: several resident templates, band-by-band
+marching of cohorts, and results that do not depend on the mix.
+
+Bars:
+* Alignment against a template table (bh_align_t) equals, bit for bit, the
+  one-template alignment of the same particles (same batch).
+* A request served in a mix of requests (several box edges, templates and
+  sizes, admitted over several ticks) gets bit-for-bit the result of the same
+  request run alone: the split-BF16 expansion of its volumes alone, the march
+  over the coarse bands on the BF16 coefficients and the final band on the
+  refined ones, all in their batch-invariant forms.
+* The served result agrees with the FP64 oracle (exact coefficients, all
+  bands) within 1 degree (the bar for the BF16-expansion form), or the two
+  winning scores tie.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+import synth.serving as ss
+from gpu_util import cuda_device, say, to_pairs
+from oracle import align as oalign, basis, expand, wigner
+
+pytestmark = pytest.mark.gpu
+
+BOXES = {16: (6, (3, 6)), 24: (10, (5, 10))}
+T_RES = 3          # resident templates per box edge
+P = 32
+STEPS = 10
+
+
+def _templates(plan, N):
+    import torch
+    blobs = ss.serving_templates()[:T_RES]
+    vols = np.stack([synth.render_blobs(b, N) for b in blobs]).astype(np.float32)
+    return plan.expand(torch.from_numpy(vols).to(cuda_device())), blobs
+
+
+def _particles(blobs, N, t, n, seed):
+    rng = np.random.default_rng(seed)
+    g = synth.quat_to_matrix(synth.haar_quaternions(rng, n))
+    v = np.stack([synth.add_noise(synth.render_blobs(blobs[t], N, g[i]), 1.0, rng) for i in range(n)])
+    return v.astype(np.float32), g
+
+
+def test_align_t_equals_single_template_align():
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    dev = cuda_device()
+    N, L = 24, 10
+    say(f"align_t vs align N={N} L={L}")
+    plan = Plan(N, L, device=0)
+    tmpl, blobs = _templates(plan, N)
+    B = 40
+    rng = np.random.default_rng(4)
+    tid = rng.integers(0, T_RES, B).astype(np.int32)
+    vols = np.concatenate([_particles(blobs, N, int(t), 1, 100 + i)[0] for i, t in enumerate(tid)])
+    a = plan.expand(torch.from_numpy(vols).to(dev))
+    starts = torch.from_numpy(synth.serving.start_pool(B, P, seed=4)).to(dev)
+    ti = torch.from_numpy(tid).to(dev)
+    for inv in (False, True):
+        mix = plan.align_t(a, tmpl, ti, (5, 10), starts, STEPS, return_all=True, batch_invariant=inv)
+        for t in range(T_RES):
+            one = plan.align(a, tmpl[t].contiguous(), (5, 10), starts, STEPS, return_all=True,
+                             batch_invariant=inv)
+            rows = torch.from_numpy(np.nonzero(tid == t)[0]).to(dev)
+            for x, y in zip(mix, one):
+                assert torch.equal(x[rows], y[rows])
+    # a one-entry table with no index is the one-template case
+    e1 = plan.align_t(a, tmpl[:1].contiguous(), None, (5, 10), starts, STEPS)
+    e2 = plan.align(a, tmpl[0].contiguous(), (5, 10), starts, STEPS)
+    assert torch.equal(e1[0], e2[0]) and torch.equal(e1[1], e2[1])
+    torch.cuda.synchronize()
+    plan.close()
+
+
+def _alone(plan, tmpl, bands, vols, t, starts):
+    """The request run by itself with direct library calls."""
+    import torch
+    dev = cuda_device()
+    n = vols.shape[0]
+    a = torch.empty((n, plan.C, 2), dtype=torch.float32, device=dev)
+    c = torch.empty_like(a)
+    plan.expand_ex(vols, "bf16x3", out=a, coarse=c, batch_invariant=True)
+    ti = torch.full((n,), t, dtype=torch.int32, device=dev)
+    x = starts.clone()
+    for L in bands[:-1]:
+        _e, _s, x, _sc = plan.align_t(c, tmpl, ti, [L], x, STEPS, return_all=True,
+                                      batch_invariant=True)
+    e, s = plan.align_t(a, tmpl, ti, [bands[-1]], x, STEPS, batch_invariant=True)
+    return e.cpu().numpy(), s.cpu().numpy()
+
+
+def test_served_result_same_alone_and_in_mix():
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd.serving import Engine, Request
+    dev = cuda_device()
+    plans = {N: Plan(N, L, device=0) for N, (L, _b) in BOXES.items()}
+    tmpls, blobs = {}, {}
+    for N in BOXES:
+        tmpls[N], blobs[N] = _templates(plans[N], N)
+    rng = np.random.default_rng(7)
+    spec = []
+    for i in range(10):
+        N = int(rng.choice(list(BOXES)))
+        spec.append((N, int(rng.integers(T_RES)), int(rng.integers(1, 40))))
+    data = []
+    for i, (N, t, n) in enumerate(spec):
+        v, _g = _particles(blobs[N], N, t, n, 1000 + i)
+        st = synth.serving.start_pool(n, P, seed=50 + i)
+        data.append((torch.from_numpy(v).to(dev), torch.from_numpy(st).to(dev)))
+    torch.cuda.synchronize()
+    say(f"serving mix of {len(spec)} requests over boxes {sorted(BOXES)}")
+    eng = Engine(BOXES, tmpls, restarts=P, steps=STEPS, plans=plans, max_cohort=48,
+                 budget_bytes=1 << 30)
+    reqs = []
+    done = []
+    # staggered submission: requests join while others are mid-march
+    for i, ((N, t, n), (v, st)) in enumerate(zip(spec, data)):
+        reqs.append(eng.submit(Request(box=N, template=t, n=n, volumes=v, starts=st)))
+        if i % 3 == 2:
+            done += eng.step()
+    done += eng.drain()
+    assert sorted(r.rid for r in done) == sorted(r.rid for r in reqs)
+    for r, (N, t, n), (v, st) in zip(reqs, spec, data):
+        e, s = _alone(plans[N], tmpls[N], BOXES[N][1], v, t, st)
+        assert r.euler.shape == (n, 3)
+        np.testing.assert_array_equal(r.euler, e)
+        np.testing.assert_array_equal(r.score, s)
+        assert r.done >= r.arrival
+    # the same request through an otherwise idle engine
+    eng2 = Engine(BOXES, tmpls, restarts=P, steps=STEPS, plans=plans)
+    for k in (0, 5):
+        (N, t, n), (v, st) = spec[k], data[k]
+        r = eng2.submit(Request(box=N, template=t, n=n, volumes=v, starts=st))
+        (out,) = eng2.drain()
+        np.testing.assert_array_equal(out.euler, reqs[k].euler)
+    torch.cuda.synchronize()
+    for p in plans.values():
+        p.close()
+
+
+def test_served_result_matches_oracle():
+    """One 24^3 particle (SNR 1) served in a mix; oracle: FP64 expansion,
+    all bands on exact coefficients, same starts."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd.serving import Engine, Request
+    dev = cuda_device()
+    N, (L, bands) = 24, BOXES[24]
+    plan = Plan(N, L, device=0)
+    tmpl, blobs = _templates(plan, N)
+    v, g = _particles(blobs, N, 1, 3, 77)
+    st = synth.serving.start_pool(3, P, seed=77)
+    say(f"served vs oracle N={N} L={L}")
+    eng = Engine({N: (L, bands)}, {N: tmpl}, restarts=P, steps=STEPS, plans={N: plan})
+    other = eng.submit(Request(box=N, template=2, n=5,
+                               volumes=torch.from_numpy(_particles(blobs, N, 2, 5, 78)[0]).to(dev),
+                               starts=torch.from_numpy(synth.serving.start_pool(5, P, 78)).to(dev)))
+    r = eng.submit(Request(box=N, template=1, n=3, volumes=torch.from_numpy(v).to(dev),
+                           starts=torch.from_numpy(st).to(dev)))
+    eng.drain()
+    assert other.done is not None
+    idx = basis.IndexSet(L)
+    b = expand.expand(synth.render_blobs(blobs[1], N)[None].astype(np.float32).astype(np.float64), idx)[0]
+    A = expand.expand(v.astype(np.float64), idx)
+    for i in range(3):
+        o = oalign.march(A[i], b, idx, bands, st[i], STEPS)
+        e_ref, s_ref = o["euler"][o["best"]], o["score"][o["best"]]
+        ang = wigner.geodesic_deg(wigner.euler_to_matrix(*r.euler[i]), wigner.euler_to_matrix(*e_ref))
+        print(f"particle {i}: served vs oracle {ang:.3f} deg, score {r.score[i]:.8g} vs {s_ref:.8g}")
+        assert ang <= 1.0 or abs(r.score[i] - s_ref) <= 1e-4 * abs(s_ref)
+        assert abs(r.score[i] - s_ref) <= 1e-3 * abs(s_ref)
+    plan.close()
