@@ -42,12 +42,14 @@ PEAK_BF16_MFMA = 2.5e15        # MI355X dense BF16 matrix, FLOP/s
 PEAK_HBM = 8.0e12              # bytes/s
 
 # Operation counts of the score/gradient evaluation:
-# per (class, l) entry of the recurrence: 8 FMA accumulations + 5 recurrence
-# operations (u, ap*sin(beta), two FMA for e, two for de/dbeta) = 25 flops;
-# per class: seeds, the two phase products, the four output updates and
-# the running powers = 57 flops.
-FLOP_PER_ENTRY = 25
-FLOP_PER_CLASS = 57
+# per (class, l) entry of the recurrence: 8 FMA accumulations (e and de/dx
+# against the two complex weights), u = ap (x - bq) (2), e' (1 FMA) and
+# de/dx' (2 FMA) = 24 flops; per class: seeds (4), the five 4-term
+# epilogue sums S, SP, D, SQ, gradient (33), the two phase rotations (12),
+# the power and q updates (2) = 51, less the 10 saved by the peeled first
+# entry (products instead of FMAs, no previous-degree term) = 41.
+FLOP_PER_ENTRY = 24
+FLOP_PER_CLASS = 41
 
 
 def band_counts(L: int):

@@ -191,7 +191,7 @@ BandTables band_tables(int L, int Lmax) {
   for (int p = 0; p <= 2 * L; ++p) {
     const int64_t entries = t.p_first[p + 1] - t.p_first[p];
     const int64_t classes = (2 * L - p) / 2 + 1;
-    cost.push_back({14 * entries + 35 * classes, p});
+    cost.push_back({13 * entries + 32 * classes, p});
   }
   std::sort(cost.begin(), cost.end(), [](const std::pair<int64_t, int>& a,
                                          const std::pair<int64_t, int>& b) {
