@@ -17,6 +17,10 @@ step rule; the rule used on both sides of the parity tests is:
 3. After the last band the restart of highest score wins (lowest index on
    ties).
 
+Optional refinements of the paper's own procedure (Newton steps on
+candidate rotations, candidates from the local maxima of the lowest band)
+are described in ``march``.
+
 All arithmetic is FP64.
 """
 
@@ -51,36 +55,120 @@ def ascent_direction(x: np.ndarray, G: np.ndarray) -> np.ndarray:
 SIN2_FLOOR = 1e-6
 
 
+NEWTON_MAX_STEP = 0.5
+
+
+def newton_direction(x: np.ndarray, G: np.ndarray, H: np.ndarray, eta0: float) -> np.ndarray:
+    """Step of a Newton band for each restart.
+
+    Where -H is positive definite (its three leading principal minors are
+    positive) the Newton step -H^{-1} grad S towards the stationary point of
+    the local quadratic model; elsewhere the natural-gradient step
+    eta0 * g^{-1} grad S of the gradient bands.  Either is scaled down to a
+    largest component of NEWTON_MAX_STEP radians.
+    """
+    nat = eta0 * ascent_direction(x, G)
+    d = np.empty_like(nat)
+    for i in range(len(x)):
+        Hn = -H[i]
+        m1 = Hn[0, 0]
+        m2 = Hn[0, 0] * Hn[1, 1] - Hn[0, 1] * Hn[1, 0]
+        m3 = np.linalg.det(Hn)
+        if m1 > 0 and m2 > 0 and m3 > 0:
+            d[i] = np.linalg.solve(Hn, G[i])
+        else:
+            d[i] = nat[i]
+        big = np.max(np.abs(d[i]))
+        if big > NEWTON_MAX_STEP:
+            d[i] *= NEWTON_MAX_STEP / big
+    return d
+
+
+def prune_candidates(x: np.ndarray, S: np.ndarray, keep: int, min_sep: float) -> np.ndarray:
+    """Indices of `keep` candidate restarts: distinct local maxima first.
+
+    Restarts are visited by decreasing score (lower index first on ties); one
+    is taken if its rotation is more than `min_sep` radians from every one
+    taken so far (angle t between rotations: 3 - tr(Ra^T Rb) = 4 sin^2(t/2)),
+    until `keep` are taken.  If fewer are distinct, the remaining slots are
+    filled with the skipped restarts in the same order.
+    """
+    order = sorted(range(len(S)), key=lambda i: (-S[i], i))
+    R = [wigner.euler_to_matrix(*e) for e in x]
+    thr = 4.0 * np.sin(0.5 * min_sep) ** 2
+    chosen = []
+    for i in order:
+        if len(chosen) == keep:
+            break
+        if all(3.0 - np.trace(R[i].T @ R[j]) > thr for j in chosen):
+            chosen.append(i)
+    if len(chosen) < keep:
+        rest = [i for i in order if i not in chosen]
+        chosen += rest[:keep - len(chosen)]
+    return np.array(chosen, dtype=np.int64)
+
+
 def march(a, b, idx: IndexSet, bands, starts, steps: int,
           step_init: float = 1.0, grow: float = 1.25, shrink: float = 0.5,
-          trace: bool = False):
+          trace: bool = False, newton_bands: int = 0, newton_steps: int = 0,
+          keep: int = 0, min_sep: float = 0.0):
     """Run the ascent for one particle.
 
     a, b: particle / template coefficients [C] (complex).
-    starts: [P, 3] Euler triples.  Returns dict with ``euler`` [P, 3],
-    ``score`` [P], ``best`` (index), and ``trace`` (list of per-band
-    [T+1, P] score arrays) if requested.
+    starts: [P, 3] Euler triples.  Returns dict with ``euler`` [P', 3],
+    ``score`` [P'], ``best`` (index), and ``trace`` (list of per-band
+    [T+1, P'] score arrays) if requested.
+
+    Options beyond the gradient bands described above:
+    * newton_bands: the last `newton_bands` bands take Newton steps instead
+      (``newton_steps`` of them, or `steps` if 0): each band evaluates
+      (S, grad, Hessian) at the carried point, sets mu = 1, then per step
+      x' = wrap(x + mu d) with d from ``newton_direction``; accept if
+      S(x') >= S(x) (mu <- min(1, mu * grow)), else mu <- mu * shrink.
+    * keep > 0 (and < P): after the first band only the restarts chosen by
+      ``prune_candidates(keep, min_sep)`` continue (P' = keep).
     """
     x = wrap_many(np.asarray(starts, dtype=np.float64))
     P = x.shape[0]
     S = np.full(P, -np.inf)
     hist = []
-    for L in bands:
+    nb = len(bands)
+    for bi, L in enumerate(bands):
         xi = sc.cross_power(a, b, idx, L)
         W = sc.curvature_weight(a, b, idx, L)
-        eta = np.full(P, step_init / W if W > 0 else 0.0)
-        S, G = sc.score_grad(xi, x)
-        band_hist = [S.copy()]
-        for _ in range(steps):
-            xt = wrap_many(x + eta[:, None] * ascent_direction(x, G))
-            St, Gt = sc.score_grad(xi, xt)
-            acc = St >= S
-            x[acc] = xt[acc]
-            S = np.where(acc, St, S)
-            G[acc] = Gt[acc]
-            eta = np.where(acc, eta * grow, eta * shrink)
-            band_hist.append(S.copy())
+        eta0 = step_init / W if W > 0 else 0.0
+        if bi >= nb - newton_bands:
+            T = newton_steps if newton_steps > 0 else steps
+            S, G, H = sc.score_grad_hess(xi, x)
+            mu = np.ones(P)
+            band_hist = [S.copy()]
+            for _ in range(T):
+                xt = wrap_many(x + mu[:, None] * newton_direction(x, G, H, eta0))
+                St, Gt, Ht = sc.score_grad_hess(xi, xt)
+                acc = St >= S
+                x[acc] = xt[acc]
+                S = np.where(acc, St, S)
+                G[acc] = Gt[acc]
+                H[acc] = Ht[acc]
+                mu = np.where(acc, np.minimum(1.0, mu * grow), mu * shrink)
+                band_hist.append(S.copy())
+        else:
+            eta = np.full(P, eta0)
+            S, G = sc.score_grad(xi, x)
+            band_hist = [S.copy()]
+            for _ in range(steps):
+                xt = wrap_many(x + eta[:, None] * ascent_direction(x, G))
+                St, Gt = sc.score_grad(xi, xt)
+                acc = St >= S
+                x[acc] = xt[acc]
+                S = np.where(acc, St, S)
+                G[acc] = Gt[acc]
+                eta = np.where(acc, eta * grow, eta * shrink)
+                band_hist.append(S.copy())
         hist.append(np.array(band_hist))
+        if bi == 0 and 0 < keep < P:
+            sel = prune_candidates(x, S, keep, min_sep)
+            x, S, P = x[sel], S[sel], keep
     best = int(np.argmax(S)) if P else -1
     out = {"euler": x, "score": S, "best": best}
     if trace:

@@ -76,6 +76,73 @@ def score(xi, euler):
     return score_grad(xi, euler)[0]
 
 
+def score_grad_hess(xi, euler):
+    """S, gradient and Hessian in (alpha, beta, gamma) at Euler triples.
+
+    Second derivatives of D^l_{mn} = e^{-i m alpha} d^l_{mn}(beta) e^{-i n gamma}:
+    alpha brings -i m, gamma brings -i n, beta replaces d by d' or d''.
+    Returns (S [P], grad [P, 3], hess [P, 3, 3]).
+    """
+    e = np.atleast_2d(np.asarray(euler, dtype=np.float64))
+    P = e.shape[0]
+    S = np.zeros(P)
+    G = np.zeros((P, 3))
+    H = np.zeros((P, 3, 3))
+    al, be, ga = e[:, 0], e[:, 1], e[:, 2]
+    for l, x in enumerate(xi):
+        if not np.any(x):
+            continue
+        m = np.arange(-l, l + 1)
+        d = wigner.small_d(l, be).reshape(P, 2 * l + 1, 2 * l + 1)
+        d1 = wigner.small_d_prime(l, be).reshape(P, 2 * l + 1, 2 * l + 1)
+        d2 = wigner.small_d_second(l, be).reshape(P, 2 * l + 1, 2 * l + 1)
+        pa = np.exp(-1j * m[None, :] * al[:, None])
+        pg = np.exp(-1j * m[None, :] * ga[:, None])
+        W = x[None] * pa[:, :, None] * pg[:, None, :]
+        fa = (-1j * m)[None, :, None]          # d/dalpha on D_{mn}
+        fg = (-1j * m)[None, None, :]          # d/dgamma on D_{mn}
+        re = lambda t: np.real(np.sum(t, axis=(1, 2)))
+        S += re(W * d)
+        G[:, 0] += re(W * d * fa)
+        G[:, 1] += re(W * d1)
+        G[:, 2] += re(W * d * fg)
+        H[:, 0, 0] += re(W * d * fa * fa)
+        H[:, 0, 1] += re(W * d1 * fa)
+        H[:, 0, 2] += re(W * d * fa * fg)
+        H[:, 1, 1] += re(W * d2)
+        H[:, 1, 2] += re(W * d1 * fg)
+        H[:, 2, 2] += re(W * d * fg * fg)
+    H[:, 1, 0] = H[:, 0, 1]
+    H[:, 2, 0] = H[:, 0, 2]
+    H[:, 2, 1] = H[:, 1, 2]
+    return S, G, H
+
+
+def degree_energy(a: np.ndarray, b: np.ndarray, idx: IndexSet, L: int) -> np.ndarray:
+    """||xi^l||_F^2 for l = 0..L: energy of each degree of the band-L cross-power."""
+    return np.array([float(np.sum(np.abs(x) ** 2)) for x in cross_power(a, b, idx, L)])
+
+
+def energy_ratio(energy: np.ndarray) -> np.ndarray:
+    """Ratio(L) = sum_{l > L} E_l / sum_l E_l for L = 0..len(E)-1 (the energy
+    of the degrees a truncation at L leaves out, as a fraction of all)."""
+    E = np.asarray(energy, dtype=np.float64)
+    tot = E.sum()
+    tail = tot - np.cumsum(E)
+    return tail / tot if tot > 0 else np.zeros_like(E)
+
+
+def select_bands(ratio: np.ndarray, thresholds) -> list:
+    """For each threshold tau (any order), the smallest L with Ratio(L) <= tau;
+    the distinct values in increasing order."""
+    r = np.asarray(ratio)
+    out = set()
+    for tau in thresholds:
+        hit = np.nonzero(r <= tau)[0]
+        out.add(int(hit[0]) if hit.size else len(r) - 1)
+    return sorted(out)
+
+
 def band_norms(a: np.ndarray, b: np.ndarray, idx: IndexSet, L: int):
     """Per-degree norms ||a_l||, ||b_l|| over band L (l = 0..L)."""
     keep = band_mask(idx, L)

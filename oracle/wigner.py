@@ -105,6 +105,13 @@ def small_d_prime(l: int, beta) -> np.ndarray:
     return np.real(np.matmul(-1j * jy, d))
 
 
+def small_d_second(l: int, beta) -> np.ndarray:
+    """d^2/dbeta^2 d^l(beta) = -J_y^2 d^l(beta) (exact matrix identity)."""
+    jy = jy_matrix(l)
+    d = small_d(l, beta)
+    return np.real(np.matmul(-(jy @ jy), d))
+
+
 def wigner_D(l: int, alpha: float, beta: float, gamma: float) -> np.ndarray:
     """D^l_{mn}(alpha, beta, gamma) = e^{-i m alpha} d^l_{mn}(beta) e^{-i n gamma}."""
     m = np.arange(-l, l + 1)
