@@ -157,6 +157,24 @@ int bh_cross_power(bh_plan* p, const float* a, const float* b, int64_t B, int L,
 int bh_correlate(bh_plan* p, const float* a, const float* b, int64_t B, int L,
                  const double* euler, int R, double* score, double* grad, void* stream);
 
+/* As bh_correlate, with the Hessian of the score in (alpha, beta, gamma)
+ * (the closed-form derivatives of Sec. II-C taken twice: alpha brings
+ * -i m, gamma -i n, beta d^l'' for d^l):
+ * hess: dev double[B][R][6] = (aa, ab, ag, bb, bg, gg); grad may be NULL. */
+int bh_correlate_hess(bh_plan* p, const float* a, const float* b, int64_t B, int L,
+                      const double* euler, int R, double* score, double* grad, double* hess,
+                      void* stream);
+
+/* ---------------------------------------------------------------------
+ * Degree energies of the band-L cross-power (Sec. II-C, energy ratio):
+ * energy[b][l] = ||xi^l||_F^2 = sum_{m,n} |xi^l_{mn}|^2, l = 0..L.
+ * The energy ratio Ratio(L') = sum_{l > L'} E_l / sum_l E_l is their tail
+ * sum; bands for the march are chosen where it falls below thresholds.
+ * energy: dev double[B][L+1].
+ * ------------------------------------------------------------------- */
+int bh_degree_energy(bh_plan* p, const float* a, const float* b, int64_t B, int L,
+                     double* energy, void* stream);
+
 /* ---------------------------------------------------------------------
  * Alignment (Sec. II-C): frequency marching over `bands` with multi-start
  * gradient ascent.  For each band L_b (each <= L_max, any order): evaluate
@@ -187,7 +205,30 @@ typedef struct {
                                work split); 0: the split may widen for
                                small batches (lower latency, summation
                                order then depends on the batch size)      */
+  int32_t newton_bands;     /* 0..n_bands: the last newton_bands bands take
+                               Newton steps (below) instead               */
+  int32_t newton_steps;     /* steps of a Newton band (0: steps_per_band)  */
+  int32_t n_keep;           /* 0: every restart runs every band; 1..64
+                               (< n_restarts <= 1024): after the first band
+                               only n_keep candidates continue (below)    */
+  double keep_min_sep;      /* radians in [0, pi]: candidates closer than
+                               this count as the same local maximum       */
 } bh_align_opts;
+
+/* Newton bands (Sec. II-C, III): evaluate S, grad S and the Hessian H at the
+ * carried point; mu = 1; then per step: d = (-H)^{-1} grad S if -H is
+ * positive definite (all leading principal minors > 0), else
+ * eta0 g^{-1} grad S with eta0 = step_init / W_b; d scaled to a largest
+ * component of at most 0.5 rad; x' = wrap(x + mu d); accept if
+ * S(x') >= S(x) (mu = min(1, mu * step_grow)) else mu *= step_shrink.
+ *
+ * Candidates (Sec. III: local maxima of the lowest band): after the first
+ * band the restarts are visited by decreasing score (lowest index first on
+ * ties) and one is kept if its rotation is farther than keep_min_sep from
+ * every one kept so far, until n_keep are kept; if fewer are that far
+ * apart, the rest are filled with the skipped restarts in the same order.
+ * The later bands run the n_keep candidates only; all_euler / all_score
+ * then hold n_keep entries per particle: [B][n_keep][3], [B][n_keep]. */
 
 int bh_align(bh_plan* p, const float* a, const float* b, int64_t B,
              const bh_align_opts* opts, const double* starts,

@@ -37,6 +37,10 @@ class AlignOpts(ctypes.Structure):
         ("step_grow", ctypes.c_double),
         ("step_shrink", ctypes.c_double),
         ("batch_invariant", ctypes.c_int32),
+        ("newton_bands", ctypes.c_int32),
+        ("newton_steps", ctypes.c_int32),
+        ("n_keep", ctypes.c_int32),
+        ("keep_min_sep", ctypes.c_double),
     ]
 
 
@@ -62,6 +66,8 @@ SIGNATURES = {
     "bh_cross_power": (_I, [_P, _P, _P, _I64, _I, _P, _P]),
     "bh_correlate": (_I, [_P, _P, _P, _I64, _I, _P, _I, _P, _P, _P]),
     "bh_align": (_I, [_P, _P, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),
+    "bh_correlate_hess": (_I, [_P, _P, _P, _I64, _I, _P, _I, _P, _P, _P, _P]),
+    "bh_degree_energy": (_I, [_P, _P, _P, _I64, _I, _P, _P]),
     "bh_align_t": (_I, [_P, _P, _P, _I, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),
     "bh_profile_enable": (_I, [_P, _I]),
     "bh_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),

@@ -183,15 +183,44 @@ class Plan:
                                  _ptr(score), _ptr(g), _stream()), "bh_correlate")
         return score, g
 
+    def correlate_hess(self, a: torch.Tensor, b: torch.Tensor, L: int, euler: torch.Tensor):
+        """Score [B, R], gradient [B, R, 3] and Hessian [B, R, 3, 3] (float64)."""
+        B = a.shape[0]
+        R = euler.shape[1]
+        _dev(a, torch.float32, (B, self.C, 2), "a")
+        _dev(b, torch.float32, (self.C, 2), "b")
+        _dev(euler, torch.float64, (B, R, 3), "euler")
+        score = torch.empty((B, R), dtype=torch.float64, device=a.device)
+        g = torch.empty((B, R, 3), dtype=torch.float64, device=a.device)
+        h6 = torch.empty((B, R, 6), dtype=torch.float64, device=a.device)
+        check(lib().bh_correlate_hess(self._h, _ptr(a), _ptr(b), B, int(L), _ptr(euler), R,
+                                      _ptr(score), _ptr(g), _ptr(h6), _stream()),
+              "bh_correlate_hess")
+        idx = torch.tensor([[0, 1, 2], [1, 3, 4], [2, 4, 5]], device=a.device)
+        return score, g, h6[:, :, idx]
+
+    def degree_energy(self, a: torch.Tensor, b: torch.Tensor, L: int) -> torch.Tensor:
+        """||xi^l||_F^2 of the band-L cross-power, [B, L+1] float64."""
+        B = a.shape[0]
+        _dev(a, torch.float32, (B, self.C, 2), "a")
+        _dev(b, torch.float32, (self.C, 2), "b")
+        out = torch.empty((B, int(L) + 1), dtype=torch.float64, device=a.device)
+        check(lib().bh_degree_energy(self._h, _ptr(a), _ptr(b), B, int(L), _ptr(out), _stream()),
+              "bh_degree_energy")
+        return out
+
     def align(self, a: torch.Tensor, b: torch.Tensor, bands: Sequence[int], starts: torch.Tensor,
               steps: int, step_init: float = 1.0, step_grow: float = 1.25,
               step_shrink: float = 0.5, return_all: bool = False,
-              batch_invariant: bool = False):
+              batch_invariant: bool = False, newton_bands: int = 0, newton_steps: int = 0,
+              keep: int = 0, min_sep: float = 0.0):
         """Best rotation per particle: (euler [B, 3], score [B]) float64.
 
-        With return_all, also the final point [B, P, 3] and score [B, P] of
-        every restart.  With batch_invariant, each particle's result is
-        independent of the batch it is aligned in.
+        With return_all, also the final point [B, P', 3] and score [B, P'] of
+        every restart (P' = keep when candidates are pruned).  With
+        batch_invariant, each particle's result is independent of the batch
+        it is aligned in.  newton_bands / newton_steps / keep / min_sep: see
+        bh_align_opts (Newton bands, candidates after the first band).
         """
         B = a.shape[0]
         P = starts.shape[1]
@@ -201,11 +230,13 @@ class Plan:
         bl = (ctypes.c_int32 * len(bands))(*[int(x) for x in bands])
         o = AlignOpts(ctypes.cast(bl, ctypes.POINTER(ctypes.c_int32)), len(bands), int(steps), P,
                       float(step_init), float(step_grow), float(step_shrink),
-                      int(bool(batch_invariant)))
+                      int(bool(batch_invariant)), int(newton_bands), int(newton_steps),
+                      int(keep), float(min_sep))
         eu = torch.empty((B, 3), dtype=torch.float64, device=a.device)
         sc = torch.empty((B,), dtype=torch.float64, device=a.device)
-        ae = torch.empty((B, P, 3), dtype=torch.float64, device=a.device) if return_all else None
-        asc = torch.empty((B, P), dtype=torch.float64, device=a.device) if return_all else None
+        Po = keep if 0 < keep < P else P
+        ae = torch.empty((B, Po, 3), dtype=torch.float64, device=a.device) if return_all else None
+        asc = torch.empty((B, Po), dtype=torch.float64, device=a.device) if return_all else None
         check(lib().bh_align(self._h, _ptr(a), _ptr(b), B, ctypes.byref(o), _ptr(starts),
                              _ptr(eu), _ptr(sc), _ptr(ae), _ptr(asc), _stream()), "bh_align")
         if return_all:
@@ -215,7 +246,8 @@ class Plan:
     def align_t(self, a: torch.Tensor, templates: torch.Tensor, tmpl_idx: torch.Tensor | None,
                 bands: Sequence[int], starts: torch.Tensor, steps: int, step_init: float = 1.0,
                 step_grow: float = 1.25, step_shrink: float = 0.5, return_all: bool = False,
-                out: tuple | None = None, batch_invariant: bool = False):
+                out: tuple | None = None, batch_invariant: bool = False, newton_bands: int = 0,
+                newton_steps: int = 0, keep: int = 0, min_sep: float = 0.0):
         """As align, with particle i matched against templates[tmpl_idx[i]].
 
         templates: [T, C, 2] float32; tmpl_idx: [B] int32 (None if T == 1).
@@ -229,23 +261,25 @@ class Plan:
         _dev(starts, torch.float64, (B, P, 3), "starts")
         if tmpl_idx is not None:
             _dev(tmpl_idx, torch.int32, (B,), "tmpl_idx")
+        Po = keep if 0 < keep < P else P
         bl = (ctypes.c_int32 * len(bands))(*[int(x) for x in bands])
         o = AlignOpts(ctypes.cast(bl, ctypes.POINTER(ctypes.c_int32)), len(bands), int(steps), P,
                       float(step_init), float(step_grow), float(step_shrink),
-                      int(bool(batch_invariant)))
+                      int(bool(batch_invariant)), int(newton_bands), int(newton_steps),
+                      int(keep), float(min_sep))
         if out is None:
             eu = torch.empty((B, 3), dtype=torch.float64, device=a.device)
             sc = torch.empty((B,), dtype=torch.float64, device=a.device)
-            ae = torch.empty((B, P, 3), dtype=torch.float64, device=a.device) if return_all else None
-            asc = torch.empty((B, P), dtype=torch.float64, device=a.device) if return_all else None
+            ae = torch.empty((B, Po, 3), dtype=torch.float64, device=a.device) if return_all else None
+            asc = torch.empty((B, Po), dtype=torch.float64, device=a.device) if return_all else None
         else:
             eu, sc, ae, asc = out
             _dev(eu, torch.float64, (B, 3), "euler_out")
             _dev(sc, torch.float64, (B,), "score_out")
             if ae is not None:
-                _dev(ae, torch.float64, (B, P, 3), "all_euler")
+                _dev(ae, torch.float64, (B, Po, 3), "all_euler")
             if asc is not None:
-                _dev(asc, torch.float64, (B, P), "all_score")
+                _dev(asc, torch.float64, (B, Po), "all_score")
         check(lib().bh_align_t(self._h, _ptr(a), _ptr(templates), T, _ptr(tmpl_idx), B,
                                ctypes.byref(o), _ptr(starts), _ptr(eu), _ptr(sc), _ptr(ae),
                                _ptr(asc), _stream()), "bh_align_t")

@@ -252,7 +252,8 @@ void bh_plan_destroy(bh_plan* p) {
   for (void* q : {(void*)p->psi, (void*)p->psi_h, (void*)p->psi_l, (void*)p->vidx, (void*)p->csrc,
                   (void*)p->csgn})
     if (q) (void)hipFree(q);
-  for (Buffer* b : {&p->gathered, &p->partial, &p->xi_scr, &p->state_scr, &p->misc_scr})
+  for (Buffer* b : {&p->gathered, &p->partial, &p->xi_scr, &p->state_scr, &p->misc_scr,
+                    &p->prune_scr})
     if (b->ptr) (void)hipFree(b->ptr);
   for (auto& kv : p->bands) free_band(kv.second);
   p->prof.destroy();
@@ -356,8 +357,9 @@ int bh_cross_power(bh_plan* p, const float* a, const float* b, int64_t B, int L,
   });
 }
 
-int bh_correlate(bh_plan* p, const float* a, const float* b, int64_t B, int L, const double* euler,
-                 int R, double* score, double* grad, void* stream) {
+static int correlate_common(bh_plan* p, const float* a, const float* b, int64_t B, int L,
+                            const double* euler, int R, double* score, double* grad, double* hess,
+                            void* stream) {
   if (!p) return set_error(BH_EINVAL, "plan is NULL");
   if (L < 0 || L > p->L_max) return set_error(BH_EINVAL, "L outside 0..L_max");
   if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
@@ -370,7 +372,36 @@ int bh_correlate(bh_plan* p, const float* a, const float* b, int64_t B, int L, c
     const DevBand* band = nullptr;
     int rc = get_band(p, L, &band);
     if (rc != BH_OK) return rc;
-    return launch_correlate(p, *band, a, b, B, euler, R, score, grad, (hipStream_t)stream);
+    return launch_correlate(p, *band, a, b, B, euler, R, score, grad, hess, (hipStream_t)stream);
+  });
+}
+
+int bh_correlate(bh_plan* p, const float* a, const float* b, int64_t B, int L, const double* euler,
+                 int R, double* score, double* grad, void* stream) {
+  return correlate_common(p, a, b, B, L, euler, R, score, grad, nullptr, stream);
+}
+
+int bh_correlate_hess(bh_plan* p, const float* a, const float* b, int64_t B, int L,
+                      const double* euler, int R, double* score, double* grad, double* hess,
+                      void* stream) {
+  if (!hess) return set_error(BH_EINVAL, "NULL buffer");
+  return correlate_common(p, a, b, B, L, euler, R, score, grad, hess, stream);
+}
+
+int bh_degree_energy(bh_plan* p, const float* a, const float* b, int64_t B, int L,
+                     double* energy, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (L < 0 || L > p->L_max) return set_error(BH_EINVAL, "L outside 0..L_max");
+  if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
+  if (B == 0) return BH_OK;
+  if (!a || !b || !energy) return set_error(BH_EINVAL, "NULL buffer");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    const DevBand* band = nullptr;
+    int rc = get_band(p, L, &band);
+    if (rc != BH_OK) return rc;
+    return launch_degree_energy(p, *band, a, b, nullptr, 1, B, energy, (hipStream_t)stream);
   });
 }
 
@@ -390,6 +421,14 @@ int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templat
   if (o->n_restarts < 1 || o->n_restarts > 65536) return set_error(BH_EINVAL, "bad restart count");
   if (!(o->step_init > 0) || !(o->step_grow > 0) || !(o->step_shrink > 0))
     return set_error(BH_EINVAL, "step parameters must be positive");
+  if (o->newton_bands < 0 || o->newton_bands > o->n_bands)
+    return set_error(BH_EINVAL, "newton_bands outside 0..n_bands");
+  if (o->newton_steps < 0 || o->newton_steps > 10000) return set_error(BH_EINVAL, "bad Newton step count");
+  if (o->n_keep < 0 || o->n_keep > 64) return set_error(BH_EINVAL, "n_keep outside 0..64");
+  if (o->n_keep > 0 && o->n_keep < o->n_restarts && o->n_restarts > kPruneMaxP)
+    return set_error(BH_EUNSUPPORTED, "candidate pruning needs n_restarts <= 1024");
+  if (!(o->keep_min_sep >= 0.0) || o->keep_min_sep > 3.141592653589793)
+    return set_error(BH_EINVAL, "keep_min_sep outside [0, pi]");
   if (B == 0) return BH_OK;
   if (!a || !templates || !starts || !euler_out || !score_out) return set_error(BH_EINVAL, "NULL buffer");
   return guarded([&]() -> int {

@@ -40,9 +40,10 @@ struct Angles {
 };
 
 // Half-angle sines and cosines are kept at least this large in magnitude
-// (sign preserved) so that the x-derivative seeds below stay finite at the
-// poles beta = 0, pi; the change to any score is far below rounding.
-constexpr double kPoleFloor = 1e-100;
+// (sign preserved) so that the x-derivative seeds below (up to 1 / s^4 for
+// the second derivative) stay finite at the poles beta = 0, pi; the change
+// to any score is far below rounding.
+constexpr double kPoleFloor = 1e-30;
 
 BH_HD inline Angles prep(double al, double be, double ga) {
   Angles A;
@@ -66,6 +67,7 @@ BH_HD inline Angles prep(double al, double be, double ga) {
 
 struct Acc {
   double S, ga, gb, gg;
+  double haa, hab, hag, hbb, hbg, hgg;   // Hessian (evaluators with HESS only)
 };
 
 // One step of the rescaled recurrence for chain entry x/c (see below):
@@ -73,7 +75,12 @@ struct Acc {
 // u = ap (x - bq) from the table entry {ap, bq}.  (Written as a subtraction
 // and a product, each instruction reads one table value: a vector
 // instruction can take only one scalar-register operand.)
-#define BH_CHAIN_STEP(X4, C2, EA, RA, EB, RB)                                 \
+// With HESS the chains carry beta-derivatives instead (no pole
+// singularity in second derivatives): with u = ap (x - bq), u' = -ap
+// sin(beta) and u'' = -ap cos(beta),
+//   r' = u r - r_prev + u' e,   q' = u q - q_prev + 2 u' r + u'' e
+// for r = de/dbeta and q = d^2e/dbeta^2.
+#define BH_CHAIN_STEP(X4, C2, EA, RA, QA, EB, RB, QB)                         \
   do {                                                                        \
     t1r = fma((X4).x, EA, t1r);                                               \
     t1i = fma((X4).y, EA, t1i);                                               \
@@ -84,8 +91,19 @@ struct Acc {
     r2r = fma((X4).z, RA, r2r);                                               \
     r2i = fma((X4).w, RA, r2i);                                               \
     const double u_ = (C2).x * (A.x - (C2).y);                                \
+    if constexpr (HESS) {                                                     \
+      q1r = fma((X4).x, QA, q1r);                                             \
+      q1i = fma((X4).y, QA, q1i);                                             \
+      q2r = fma((X4).z, QA, q2r);                                             \
+      q2i = fma((X4).w, QA, q2i);                                             \
+      const double du_ = (C2).x * A.msb;                                      \
+      const double dd_ = (C2).x * mx;                                         \
+      QB = fma(dd_, EA, fma(du_ + du_, RA, fma(u_, QA, -QB)));                \
+      RB = fma(du_, EA, fma(u_, RA, -RB));                                    \
+    } else {                                                                  \
+      RB = fma((C2).x, EA, fma(u_, RA, -RB));                                 \
+    }                                                                         \
     EB = fma(u_, EA, -EB);                                                    \
-    RB = fma((C2).x, EA, fma(u_, RA, -RB));                                   \
   } while (0)
 
 // Partial sums of one wave over the classes of its p-groups: plist holds
@@ -110,10 +128,18 @@ struct Acc {
 // the alpha and gamma derivatives m I1 + n I2 and n I1 + m I2 (I = Im(W t))
 // are accumulated as (p SP +- SQ) / 2 with SP = sum (I1 + I2) and
 // SQ = sum q (I1 - I2) over the p-group.
+//
+// HESS (second derivatives, m = (p+q)/2, n = (p-q)/2; chains in beta):
+//   d2/dalpha2  = -sum m^2 Re z1 + n^2 Re z2,  d2/dgamma2 with m, n swapped,
+//   d2/dalpha dgamma = -sum mn (Re z1 + Re z2)   (z = W t),
+// written with the per-p sums A0 = sum (Re z1 + Re z2), A2 = sum q^2 (...),
+// B1 = sum q (Re z1 - Re z2); the mixed beta terms m Im(W1 r1) + n Im(W2 r2)
+// (and swapped) through ZP, ZQ as SP, SQ; d2/dbeta2 = Re(W1 q1 + W2 q2).
+template <bool HESS>
 BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, int L,
                            const int32_t* __restrict__ p_first,
                            const double* __restrict__ rec, const double* __restrict__ X) {
-  Acc acc = {0.0, 0.0, 0.0, 0.0};
+  Acc acc = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int np = plist[0];
 #if !BH_SCORE_PHASE_SINCOS
   // Phi = e^{-i pc sigma} and cp = c^pc, advanced along the ascending
@@ -127,6 +153,12 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
 #endif
   const double s2 = A.s * A.s;
   const cplx th2c = {A.th2.re, -A.th2.im};
+  double qsum = 0.0, zpx = 0.0, zgx = 0.0;     // HESS: sum Re(W q), mixed-beta sums
+  const double mx = -A.x;
+  // HESS: c^{p-2} .. c^{p+2} (negative powers stand as 0: their
+  // coefficients vanish), advanced with p
+  double cw[5] = {0.0, 0.0, 1.0, A.c, A.c * A.c};
+  int pw = 0;
   for (int j = 0; j < np; ++j) {
     const int p = plist[1 + j];
 #if BH_SCORE_PHASE_SINCOS
@@ -142,6 +174,15 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
     }
 #endif
     const double pic2 = (double)p * A.ic2;
+    if constexpr (HESS) {
+      for (; pw < p; ++pw) {
+        cw[0] = cw[1];
+        cw[1] = cw[2];
+        cw[2] = cw[3];
+        cw[3] = cw[4];
+        cw[4] *= A.c;
+      }
+    }
     int off = p_first[p];
     const int q0 = p & 1;
     cplx W1 = q0 ? cmul(Phi, A.th1) : Phi;
@@ -149,16 +190,32 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
     double sq = q0 ? A.s : 1.0;       // s^q
     double qd = (double)q0;
     double SP = 0.0, SQ = 0.0;
+    double A0 = 0.0, A2 = 0.0, B1 = 0.0, ZP = 0.0, ZQ = 0.0;
+    // HESS: s^{q-2} .. s^{q+2} (as cw), advanced by two per class
+    double sw[5] = {0.0, q0 ? 1.0 : 0.0, q0 ? A.s : 1.0, q0 ? s2 : A.s, q0 ? s2 * A.s : s2};
     for (int q = q0; q <= 2 * L - p; q += 2) {
       const int m = (p + q) >> 1;
       const int rem = L - m;          // chain entries after the first
       const double4* Xc = reinterpret_cast<const double4*>(X) + off;
       const double2* Rc = reinterpret_cast<const double2*>(rec) + off;
-      // seeds: e_m = c^p s^q and de_m/dx = e_m (p / (4 c^2) - q / (4 s^2));
-      // the peeled first step starts the sums and yields e_{m+1}.
-      double eb = cp * sq;
-      double rb = eb * fma(-qd, A.is2, pic2);
+      // seeds: e_m = c^p s^q and de_m/dx = e_m (p / (4c^2) - q / (4s^2)); with
+      // HESS de_m/dbeta = (q c^{p+1} s^{q-1} - p c^{p-1} s^{q+1}) / 2 and
+      // d2e_m/dbeta2 = (q(q-1) c^{p+2} s^{q-2} + p(p-1) c^{p-2} s^{q+2}
+      //                 - (q(p+1) + p(q+1)) c^p s^q) / 4.
+      // The peeled first step starts the sums and yields e_{m+1}.
+      double eb, rb, qb = 0.0;
+      if constexpr (HESS) {
+        const double pd = (double)p;
+        eb = cw[2] * sw[2];
+        rb = 0.5 * (qd * cw[3] * sw[1] - pd * cw[1] * sw[3]);
+        qb = 0.25 * (qd * (qd - 1.0) * cw[4] * sw[0] + pd * (pd - 1.0) * cw[0] * sw[4] -
+                     (qd * (pd + 1.0) + pd * (qd + 1.0)) * eb);
+      } else {
+        eb = cp * sq;
+        rb = eb * fma(-qd, A.is2, pic2);
+      }
       double t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i, ea, ra;
+      double q1r = 0.0, q1i = 0.0, q2r = 0.0, q2i = 0.0, qa = 0.0;
       {
         const double4 x0 = Xc[0];
         const double2 c0_ = Rc[0];
@@ -172,7 +229,17 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
         r2i = x0.w * rb;
         const double u_ = c0_.x * (A.x - c0_.y);
         ea = u_ * eb;
-        ra = fma(c0_.x, eb, u_ * rb);
+        if constexpr (HESS) {
+          q1r = x0.x * qb;
+          q1i = x0.y * qb;
+          q2r = x0.z * qb;
+          q2i = x0.w * qb;
+          const double du_ = c0_.x * A.msb;
+          qa = fma(c0_.x * mx, eb, fma(du_ + du_, rb, u_ * qb));
+          ra = fma(du_, eb, u_ * rb);
+        } else {
+          ra = fma(c0_.x, eb, u_ * rb);
+        }
       }
       // Full rounds of four entries: straight-line code, one load batch and
       // one wait per round.  Then a tail of two and/or one entries.
@@ -181,27 +248,45 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
       for (; i <= n4; i += 4) {
         const double4 x0 = Xc[i], x1 = Xc[i + 1], x2 = Xc[i + 2], x3 = Xc[i + 3];
         const double2 c0_ = Rc[i], c1 = Rc[i + 1], c2 = Rc[i + 2], c3 = Rc[i + 3];
-        BH_CHAIN_STEP(x0, c0_, ea, ra, eb, rb);
-        BH_CHAIN_STEP(x1, c1, eb, rb, ea, ra);
-        BH_CHAIN_STEP(x2, c2, ea, ra, eb, rb);
-        BH_CHAIN_STEP(x3, c3, eb, rb, ea, ra);
+        BH_CHAIN_STEP(x0, c0_, ea, ra, qa, eb, rb, qb);
+        BH_CHAIN_STEP(x1, c1, eb, rb, qb, ea, ra, qa);
+        BH_CHAIN_STEP(x2, c2, ea, ra, qa, eb, rb, qb);
+        BH_CHAIN_STEP(x3, c3, eb, rb, qb, ea, ra, qa);
       }
       if (rem & 2) {
         const double4 x0 = Xc[i], x1 = Xc[i + 1];
         const double2 c0_ = Rc[i], c1 = Rc[i + 1];
-        BH_CHAIN_STEP(x0, c0_, ea, ra, eb, rb);
-        BH_CHAIN_STEP(x1, c1, eb, rb, ea, ra);
+        BH_CHAIN_STEP(x0, c0_, ea, ra, qa, eb, rb, qb);
+        BH_CHAIN_STEP(x1, c1, eb, rb, qb, ea, ra, qa);
         i += 2;
       }
       if (rem & 1) {
         const double4 x0 = Xc[i];
         const double2 c0_ = Rc[i];
-        BH_CHAIN_STEP(x0, c0_, ea, ra, eb, rb);
+        BH_CHAIN_STEP(x0, c0_, ea, ra, qa, eb, rb, qb);
       }
-      acc.S = fma(W1.re, t1r, acc.S);
-      acc.S = fma(-W1.im, t1i, acc.S);
-      acc.S = fma(W2.re, t2r, acc.S);
-      acc.S = fma(-W2.im, t2i, acc.S);
+      if constexpr (HESS) {
+        const double z1 = fma(W1.re, t1r, -W1.im * t1i);
+        const double z2 = fma(W2.re, t2r, -W2.im * t2i);
+        const double zs = z1 + z2;
+        acc.S += zs;
+        A0 += zs;
+        A2 = fma(qd * qd, zs, A2);
+        B1 = fma(qd, z1 - z2, B1);
+        const double y1 = fma(W1.re, r1i, W1.im * r1r);
+        const double y2 = fma(W2.re, r2i, W2.im * r2r);
+        ZP += y1 + y2;
+        ZQ = fma(qd, y1 - y2, ZQ);
+        qsum = fma(W1.re, q1r, qsum);
+        qsum = fma(-W1.im, q1i, qsum);
+        qsum = fma(W2.re, q2r, qsum);
+        qsum = fma(-W2.im, q2i, qsum);
+      } else {
+        acc.S = fma(W1.re, t1r, acc.S);
+        acc.S = fma(-W1.im, t1i, acc.S);
+        acc.S = fma(W2.re, t2r, acc.S);
+        acc.S = fma(-W2.im, t2i, acc.S);
+      }
       SP = fma(W1.re, t1i, SP);
       SP = fma(W1.im, t1r, SP);
       SP = fma(W2.re, t2i, SP);
@@ -220,12 +305,34 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
       W2 = cmul(W2, th2c);
       sq *= s2;
       qd += 2.0;
+      if constexpr (HESS) {
+        sw[0] = sw[2];
+        sw[1] = sw[3];
+        sw[2] = sw[4];
+        sw[3] *= s2;
+        sw[4] *= s2;
+      }
     }
-    const double pSP = (double)p * SP;
+    const double pd = (double)p;
+    const double pSP = pd * SP;
     acc.ga += 0.5 * (pSP + SQ);
     acc.gg += 0.5 * (pSP - SQ);
+    if constexpr (HESS) {
+      const double pp = pd * pd * A0;
+      acc.haa -= 0.25 * (pp + A2 + 2.0 * pd * B1);
+      acc.hgg -= 0.25 * (pp + A2 - 2.0 * pd * B1);
+      acc.hag -= 0.25 * (pp - A2);
+      zpx += 0.5 * (pd * ZP + ZQ);
+      zgx += 0.5 * (pd * ZP - ZQ);
+    }
   }
-  acc.gb *= A.msb;
+  if constexpr (HESS) {
+    acc.hab = zpx;
+    acc.hbg = zgx;
+    acc.hbb = qsum;
+  } else {
+    acc.gb *= A.msb;
+  }
   return acc;
 }
 #undef BH_CHAIN_STEP

@@ -36,6 +36,10 @@ constexpr int kGemmKAlign = kGemmBK * 16;   // V padded to this, split-K <= 16
 // cross-power buffers carry this many zero entries past their end.
 constexpr int kTablePad = 4;
 
+// Largest restart count for which candidates can be pruned after the first
+// band (the pruning kernel ranks the restarts of a particle in LDS).
+constexpr int kPruneMaxP = 1024;
+
 // Device copy of one band's score tables (see BandTables).
 struct DevBand {
   int L = -1;
@@ -86,7 +90,7 @@ struct bh_plan {
   float* csgn = nullptr;         // [C][2] sign applied to it
   std::vector<int64_t> band_size;   // C(L) for L = 0..L_max
   // scratch (grown on demand, owned by the plan)
-  bh::Buffer gathered, partial, xi_scr, state_scr, misc_scr;
+  bh::Buffer gathered, partial, xi_scr, state_scr, misc_scr, prune_scr;
   std::map<int, bh::DevBand> bands;
   bh::Profiler prof;
 };
@@ -130,7 +134,11 @@ int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, fl
 int launch_cross_power_dense(bh_plan* p, const DevBand& band, const float* a, const float* b,
                              int64_t B, double* xi, hipStream_t s);
 int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const float* b, int64_t B,
-                     const double* euler, int R, double* score, double* grad, hipStream_t s);
+                     const double* euler, int R, double* score, double* grad, double* hess,
+                     hipStream_t s);
+int launch_degree_energy(bh_plan* p, const DevBand& band, const float* a, const float* b,
+                         const int32_t* tmpl, int n_tmpl, int64_t B, double* energy,
+                         hipStream_t s);
 int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl, int n_tmpl,
                  int64_t B, const bh_align_opts& o,
                  const double* starts, double* euler_out, double* score_out, double* all_euler,

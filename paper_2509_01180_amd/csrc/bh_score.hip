@@ -50,6 +50,9 @@ constexpr double kSin2Floor = 1e-6;
 #else
 #define BH_SCORE_OCCUPANCY
 #endif
+// The Hessian evaluators carry four more chain sums and a longer epilogue;
+// they are given up to 128 registers (4 waves per SIMD) instead.
+#define BH_HESS_OCCUPANCY(H) __attribute__((amdgpu_waves_per_eu((H) ? 4 : BH_SCORE_WAVES_PER_EU)))
 
 // ------------------------------------------------------------ cross-power --
 
@@ -148,21 +151,25 @@ __global__ void k_band_weight(const float* __restrict__ a, const float* __restri
   }
 }
 
-// Sum the W wave partials (fixed order) through LDS buffer `buf`.
-__device__ inline Acc reduce_waves(Acc mine, double* buf, int wave, int lane, int W) {
-  buf[(wave * 4 + 0) * 64 + lane] = mine.S;
-  buf[(wave * 4 + 1) * 64 + lane] = mine.ga;
-  buf[(wave * 4 + 2) * 64 + lane] = mine.gb;
-  buf[(wave * 4 + 3) * 64 + lane] = mine.gg;
-  __syncthreads();
-  Acc t = {0.0, 0.0, 0.0, 0.0};
+// Sum the W wave partials (fixed order) through LDS buffer `buf`
+// ([W][NV][64]); NV = 4 (score, gradient) or 10 (and the Hessian).
+template <int NV>
+__device__ inline void store_partials(const Acc& mine, double* buf, int wave, int lane) {
+  const double v[10] = {mine.S, mine.ga, mine.gb, mine.gg, mine.haa,
+                        mine.hab, mine.hag, mine.hbb, mine.hbg, mine.hgg};
+#pragma unroll
+  for (int k = 0; k < NV; ++k) buf[(wave * NV + k) * 64 + lane] = v[k];
+}
+
+template <int NV>
+__device__ inline Acc sum_partials(const double* buf, int lane, int W) {
+  double v[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
   for (int w = 0; w < W; ++w) {
-    t.S += buf[(w * 4 + 0) * 64 + lane];
-    t.ga += buf[(w * 4 + 1) * 64 + lane];
-    t.gb += buf[(w * 4 + 2) * 64 + lane];
-    t.gg += buf[(w * 4 + 3) * 64 + lane];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += buf[(w * NV + k) * 64 + lane];
   }
-  return t;
+  return Acc{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9]};
 }
 
 __device__ inline double wrap_pi(double t) { return t - kTwoPi * floor((t + kPi) / kTwoPi); }
@@ -178,15 +185,16 @@ __device__ inline void wrap_euler(double& a, double& b, double& g) {
   g = wrap_pi(g);
 }
 
-template <int W>
-__global__ __launch_bounds__(64 * W) BH_SCORE_OCCUPANCY void k_correlate(
+// Score, gradient and (HESS) Hessian at R rotations per particle; hess
+// holds (aa, ab, ag, bb, bg, gg) per rotation.
+template <int W, bool HESS>
+__global__ __launch_bounds__(64 * W) BH_HESS_OCCUPANCY(HESS) void k_correlate(
     const int32_t* __restrict__ p_first, const int32_t* __restrict__ wave_p,
-                                                      const double* __restrict__ rec,
-                                                      const double* __restrict__ X, int64_t n_entries,
-                                                      int L, const double* __restrict__ euler, int R,
-                                                      double* __restrict__ score,
-                                                      double* __restrict__ grad) {
-  __shared__ double buf[W * 4 * 64];
+    const double* __restrict__ rec, const double* __restrict__ X, int64_t n_entries, int L,
+    const double* __restrict__ euler, int R, double* __restrict__ score,
+    double* __restrict__ grad, double* __restrict__ hess) {
+  constexpr int NV = HESS ? 10 : 4;
+  __shared__ double buf[W * NV * 64];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t pb = blockIdx.y;
@@ -200,15 +208,76 @@ __global__ __launch_bounds__(64 * W) BH_SCORE_OCCUPANCY void k_correlate(
     ga = eu[2];
   }
   const Angles A = prep(al, be, ga);
-  const Acc mine = eval_wave(A, wave_p + wave * (2 * L + 2), L, p_first, rec, X + pb * n_entries * 4);
-  const Acc t = reduce_waves(mine, buf, wave, lane, W);
+  const Acc mine =
+      eval_wave<HESS>(A, wave_p + wave * (2 * L + 2), L, p_first, rec, X + pb * n_entries * 4);
+  store_partials<NV>(mine, buf, wave, lane);
+  __syncthreads();
   if (wave == 0 && active) {
+    const Acc t = sum_partials<NV>(buf, lane, W);
     score[pb * R + r] = t.S;
     if (grad) {
       grad[(pb * R + r) * 3 + 0] = t.ga;
       grad[(pb * R + r) * 3 + 1] = t.gb;
       grad[(pb * R + r) * 3 + 2] = t.gg;
     }
+    if constexpr (HESS) {
+      double* h = hess + (pb * R + r) * 6;
+      h[0] = t.haa;
+      h[1] = t.hab;
+      h[2] = t.hag;
+      h[3] = t.hbb;
+      h[4] = t.hbg;
+      h[5] = t.hgg;
+    }
+  }
+}
+
+// Natural-gradient direction g^{-1} grad S in ZYZ Euler coordinates, with
+// sin^2(beta) floored (the metric is singular at the poles).
+__device__ inline void natural_gradient(double xb, double ga, double gb, double gg, double& da,
+                                        double& db, double& dg) {
+  const double cb = cos(xb);
+  double s2 = 1.0 - cb * cb;
+  s2 = s2 > kSin2Floor ? s2 : kSin2Floor;
+  da = (ga - cb * gg) / s2;
+  db = gb;
+  dg = (gg - cb * ga) / s2;
+}
+
+// Step of a Newton band: (-H)^{-1} grad S where -H is positive definite
+// (leading principal minors positive; solved with the adjugate), else
+// eta0 times the natural gradient; scaled to a largest component of at most
+// kNewtonMaxStep radians.  h = (aa, ab, ag, bb, bg, gg).
+constexpr double kNewtonMaxStep = 0.5;
+
+__device__ inline void newton_direction(double xb, double ga, double gb, double gg,
+                                        const double* h, double eta0, double& da, double& db,
+                                        double& dg) {
+  const double n11 = -h[0], n12 = -h[1], n13 = -h[2], n22 = -h[3], n23 = -h[4], n33 = -h[5];
+  const double m2 = n11 * n22 - n12 * n12;
+  const double c11 = n22 * n33 - n23 * n23;
+  const double c12 = n13 * n23 - n12 * n33;
+  const double c13 = n12 * n23 - n13 * n22;
+  const double det = n11 * c11 + n12 * c12 + n13 * c13;
+  if (n11 > 0.0 && m2 > 0.0 && det > 0.0) {
+    const double c22 = n11 * n33 - n13 * n13;
+    const double c23 = n12 * n13 - n11 * n23;
+    const double c33 = m2;
+    da = (c11 * ga + c12 * gb + c13 * gg) / det;
+    db = (c12 * ga + c22 * gb + c23 * gg) / det;
+    dg = (c13 * ga + c23 * gb + c33 * gg) / det;
+  } else {
+    natural_gradient(xb, ga, gb, gg, da, db, dg);
+    da *= eta0;
+    db *= eta0;
+    dg *= eta0;
+  }
+  const double big = fmax(fabs(da), fmax(fabs(db), fabs(dg)));
+  if (big > kNewtonMaxStep) {
+    const double f = kNewtonMaxStep / big;
+    da *= f;
+    db *= f;
+    dg *= f;
   }
 }
 
@@ -216,26 +285,31 @@ __global__ __launch_bounds__(64 * W) BH_SCORE_OCCUPANCY void k_correlate(
 //
 // Every evaluation is split over the W waves; the ascent state of the 64
 // lanes lives in LDS and is updated by wave 0 between two barriers, so the
-// other waves carry no optimiser state through the evaluation.
-enum { ST_XA, ST_XB, ST_XG, ST_S, ST_GA, ST_GB, ST_GG, ST_ETA, ST_TA, ST_TB, ST_TG, ST_N };
+// other waves carry no optimiser state through the evaluation.  NEWTON:
+// Newton steps from the Hessian (ST_ETA holds the damping mu <= 1).
+enum {
+  ST_XA, ST_XB, ST_XG, ST_S, ST_GA, ST_GB, ST_GG, ST_ETA, ST_TA, ST_TB, ST_TG,
+  ST_HAA, ST_HAB, ST_HAG, ST_HBB, ST_HBG, ST_HGG, ST_ETA0, ST_N
+};
 
-template <int W>
-__global__ __launch_bounds__(64 * W) BH_SCORE_OCCUPANCY void k_march(
+template <int W, bool NEWTON>
+__global__ __launch_bounds__(64 * W) BH_HESS_OCCUPANCY(NEWTON) void k_march(
     const int32_t* __restrict__ p_first, const int32_t* __restrict__ wave_p,
-                                                  const double* __restrict__ rec,
-                                                  const double* __restrict__ X, int64_t n_entries,
-                                                  int L, const double* __restrict__ Wb, int P,
-                                                  int steps, double step_init, double grow,
-                                                  double shrink, double* __restrict__ state,
-                                                  double* __restrict__ sscore) {
-  __shared__ double red[W * 4 * 64];
-  __shared__ double st[ST_N * 64];
+    const double* __restrict__ rec, const double* __restrict__ X, int64_t n_entries, int L,
+    const double* __restrict__ Wb, int P, int steps, double step_init, double grow,
+    double shrink, double* __restrict__ state, double* __restrict__ sscore) {
+  constexpr int NV = NEWTON ? 10 : 4;
+  constexpr int NS = NEWTON ? ST_N : ST_HAA;
+  __shared__ double red[W * NV * 64];
+  __shared__ double st[NS * 64];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t pb = blockIdx.y;
   const int64_t r = (int64_t)blockIdx.x * 64 + lane;
   const bool active = r < P;
   const double* Xp = X + pb * n_entries * 4;
+  const double wb = Wb[pb];
+  const double eta0 = (wb > 0.0) ? step_init / wb : 0.0;
   if (wave == 0) {
     double xa = 0.0, xb = 0.0, xg = 0.0;
     if (active) {
@@ -245,29 +319,19 @@ __global__ __launch_bounds__(64 * W) BH_SCORE_OCCUPANCY void k_march(
       xg = s0[2];
     }
     wrap_euler(xa, xb, xg);
-    const double wb = Wb[pb];
     st[ST_TA * 64 + lane] = xa;
     st[ST_TB * 64 + lane] = xb;
     st[ST_TG * 64 + lane] = xg;
-    st[ST_ETA * 64 + lane] = (wb > 0.0) ? step_init / wb : 0.0;
+    st[ST_ETA * 64 + lane] = NEWTON ? 1.0 : eta0;
   }
   __syncthreads();
   for (int t = 0; t <= steps; ++t) {
     const Angles A = prep(st[ST_TA * 64 + lane], st[ST_TB * 64 + lane], st[ST_TG * 64 + lane]);
-    const Acc mine = eval_wave(A, wave_p + wave * (2 * L + 2), L, p_first, rec, Xp);
-    red[(wave * 4 + 0) * 64 + lane] = mine.S;
-    red[(wave * 4 + 1) * 64 + lane] = mine.ga;
-    red[(wave * 4 + 2) * 64 + lane] = mine.gb;
-    red[(wave * 4 + 3) * 64 + lane] = mine.gg;
+    const Acc mine = eval_wave<NEWTON>(A, wave_p + wave * (2 * L + 2), L, p_first, rec, Xp);
+    store_partials<NV>(mine, red, wave, lane);
     __syncthreads();
     if (wave == 0) {
-      Acc tr = {0.0, 0.0, 0.0, 0.0};
-      for (int w = 0; w < W; ++w) {
-        tr.S += red[(w * 4 + 0) * 64 + lane];
-        tr.ga += red[(w * 4 + 1) * 64 + lane];
-        tr.gb += red[(w * 4 + 2) * 64 + lane];
-        tr.gg += red[(w * 4 + 3) * 64 + lane];
-      }
+      const Acc tr = sum_partials<NV>(red, lane, W);
       double eta = st[ST_ETA * 64 + lane];
       // t == 0: the carried point itself; later: accept if not worse
       const bool take = (t == 0) || (tr.S >= st[ST_S * 64 + lane]);
@@ -279,21 +343,39 @@ __global__ __launch_bounds__(64 * W) BH_SCORE_OCCUPANCY void k_march(
         st[ST_GA * 64 + lane] = tr.ga;
         st[ST_GB * 64 + lane] = tr.gb;
         st[ST_GG * 64 + lane] = tr.gg;
+        if constexpr (NEWTON) {
+          st[ST_HAA * 64 + lane] = tr.haa;
+          st[ST_HAB * 64 + lane] = tr.hab;
+          st[ST_HAG * 64 + lane] = tr.hag;
+          st[ST_HBB * 64 + lane] = tr.hbb;
+          st[ST_HBG * 64 + lane] = tr.hbg;
+          st[ST_HGG * 64 + lane] = tr.hgg;
+        }
       }
-      if (t > 0) eta *= take ? grow : shrink;
+      if (t > 0) {
+        if (NEWTON)
+          eta = take ? fmin(1.0, eta * grow) : eta * shrink;
+        else
+          eta *= take ? grow : shrink;
+      }
       st[ST_ETA * 64 + lane] = eta;
       if (t < steps) {
-        // natural-gradient step from the current point
         const double xa = st[ST_XA * 64 + lane], xb = st[ST_XB * 64 + lane],
                      xg = st[ST_XG * 64 + lane];
         const double ga = st[ST_GA * 64 + lane], gb = st[ST_GB * 64 + lane],
                      gg = st[ST_GG * 64 + lane];
-        const double cb = cos(xb);
-        double s2 = 1.0 - cb * cb;
-        s2 = s2 > kSin2Floor ? s2 : kSin2Floor;
-        double ta = xa + eta * ((ga - cb * gg) / s2);
-        double tb = xb + eta * gb;
-        double tg = xg + eta * ((gg - cb * ga) / s2);
+        double da, db, dg;
+        if constexpr (NEWTON) {
+          const double h[6] = {st[ST_HAA * 64 + lane], st[ST_HAB * 64 + lane],
+                               st[ST_HAG * 64 + lane], st[ST_HBB * 64 + lane],
+                               st[ST_HBG * 64 + lane], st[ST_HGG * 64 + lane]};
+          newton_direction(xb, ga, gb, gg, h, eta0, da, db, dg);
+        } else {
+          natural_gradient(xb, ga, gb, gg, da, db, dg);
+        }
+        double ta = xa + eta * da;
+        double tb = xb + eta * db;
+        double tg = xg + eta * dg;
         wrap_euler(ta, tb, tg);
         st[ST_TA * 64 + lane] = ta;
         st[ST_TB * 64 + lane] = tb;
@@ -344,6 +426,128 @@ __global__ __launch_bounds__(64) void k_select(const double* __restrict__ state,
   }
 }
 
+// Rotation matrix R_z(a) R_y(b) R_z(g), row-major.
+__device__ inline void euler_matrix(double a, double b, double g, double* R) {
+  double sa, ca, sb, cb, sg, cg;
+  sincos(a, &sa, &ca);
+  sincos(b, &sb, &cb);
+  sincos(g, &sg, &cg);
+  R[0] = ca * cb * cg - sa * sg;
+  R[1] = -ca * cb * sg - sa * cg;
+  R[2] = ca * sb;
+  R[3] = sa * cb * cg + ca * sg;
+  R[4] = -sa * cb * sg + ca * cg;
+  R[5] = sa * sb;
+  R[6] = -sb * cg;
+  R[7] = sb * sg;
+  R[8] = cb;
+}
+
+// Candidates after the first band: visit the restarts by decreasing score
+// (lower index first on ties) and take one if 3 - tr(Rc^T Rj) > thr for
+// every taken j (thr = 4 sin^2(min_sep / 2): farther than min_sep), until K
+// are taken; fill any remaining slots with the skipped restarts in the same
+// order.  One wave per particle; lane j holds the matrix of the j-th taken
+// restart (K <= 64).
+__global__ __launch_bounds__(64) void k_prune(const double* __restrict__ state,
+                                              const double* __restrict__ sscore, int P, int K,
+                                              double thr, double* __restrict__ out_state,
+                                              double* __restrict__ out_score) {
+  __shared__ int order[kPruneMaxP];
+  __shared__ int chosen[64];
+  __shared__ unsigned char taken[kPruneMaxP];
+  const int64_t pb = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double* S = sscore + pb * P;
+  const double* x = state + pb * P * 3;
+  // a NaN score ranks as -infinity, so the ranks are a permutation
+  for (int i = lane; i < P; i += 64) {
+    const double si = isnan(S[i]) ? -INFINITY : S[i];
+    int rank = 0;
+    for (int j = 0; j < P; ++j) {
+      const double sj = isnan(S[j]) ? -INFINITY : S[j];
+      rank += (sj > si || (sj == si && j < i)) ? 1 : 0;
+    }
+    order[rank] = i;
+    taken[i] = 0;
+  }
+  __syncthreads();
+  double Rm[9];                 // this lane's taken restart (lane < n)
+  int n = 0;
+  for (int s = 0; s < P && n < K; ++s) {
+    const int c = order[s];
+    double Rc[9];
+    euler_matrix(x[c * 3], x[c * 3 + 1], x[c * 3 + 2], Rc);
+    bool close = false;
+    if (lane < n) {
+      double tr = 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) tr += Rc[k] * Rm[k];
+      close = !(3.0 - tr > thr);
+    }
+    if (!__any(close)) {
+      if (lane == n) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Rm[k] = Rc[k];
+        chosen[n] = c;
+        taken[c] = 1;
+      }
+      ++n;
+    }
+    __syncthreads();
+  }
+  for (int s = 0; s < P && n < K; ++s) {
+    const int c = order[s];
+    if (!taken[c]) {
+      if (lane == 0) chosen[n] = c;
+      ++n;
+    }
+  }
+  __syncthreads();
+  for (int k = lane; k < K; k += 64) {
+    const int c = chosen[k];
+    out_state[(pb * K + k) * 3 + 0] = x[c * 3 + 0];
+    out_state[(pb * K + k) * 3 + 1] = x[c * 3 + 1];
+    out_state[(pb * K + k) * 3 + 2] = x[c * 3 + 2];
+    out_score[pb * K + k] = S[c];
+  }
+}
+
+// ||xi^l||_F^2 of the band-L cross-power for l = 0..L; one block per particle.
+__global__ __launch_bounds__(256) void k_degree_energy(
+    const float* __restrict__ a, const float* __restrict__ btab, int64_t C,
+    const int32_t* __restrict__ tmpl, int n_tmpl, int L, const int32_t* __restrict__ deg_start,
+    const int32_t* __restrict__ deg_off, double* __restrict__ energy) {
+  __shared__ double part[256];
+  const int64_t pb = blockIdx.x;
+  const float* ap = a + pb * 2 * C;
+  const float* b = btab + template_of(tmpl, n_tmpl, pb) * 2 * C;
+  for (int l = 0; l <= L; ++l) {
+    const int w = 2 * l + 1;
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < w * w; t += 256) {
+      const int m = t / w - l, n = t % w - l;
+      double sre = 0.0, sim = 0.0;
+      for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
+        const int o = deg_off[i];
+        const double br = b[2 * (o + l + m)], bi = b[2 * (o + l + m) + 1];
+        const double ar = ap[2 * (o + l + n)], ai = ap[2 * (o + l + n) + 1];
+        sre += br * ar + bi * ai;
+        sim += br * ai - bi * ar;
+      }
+      acc += sre * sre + sim * sim;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) energy[pb * (L + 1) + l] = part[0];
+    __syncthreads();
+  }
+}
+
 int pick_waves(int64_t groups, int L, bool batch_invariant = false) {
   if (BH_SCORE_FIXED_W > 0) return BH_SCORE_FIXED_W;
   // Measured on MI355X (1000 particles x 64 restarts, bands 8..32): 12 waves
@@ -357,26 +561,58 @@ int pick_waves(int64_t groups, int L, bool batch_invariant = false) {
   return W;
 }
 
-template <int W>
+template <int W, bool HESS>
 void launch_correlate_w(bh_plan* p, dim3 grid, hipStream_t s, const DevBand& band, const double* X,
-                        int L, const double* euler, int R, double* score, double* grad) {
-  ProfScope ps(p, "correlate_L" + std::to_string(L), s,
+                        int L, const double* euler, int R, double* score, double* grad,
+                        double* hess) {
+  ProfScope ps(p, (HESS ? "correlate_hess_L" : "correlate_L") + std::to_string(L), s,
                (int64_t)grid.y * R * band.n_entries);
-  hipLaunchKernelGGL(k_correlate<W>, grid, dim3(64 * W), 0, s, band.p_first,
-                     band.wave_p + wave_block_offset(L, W), band.rec, X,
-                     band.n_entries, L, euler, R, score, grad);
+  hipLaunchKernelGGL((k_correlate<W, HESS>), grid, dim3(64 * W), 0, s, band.p_first,
+                     band.wave_p + wave_block_offset(L, W), band.rec, X, band.n_entries, L, euler,
+                     R, score, grad, hess);
 }
 
-template <int W>
+template <bool HESS>
+void launch_correlate_any(int W, bh_plan* p, dim3 grid, hipStream_t s, const DevBand& band,
+                          const double* X, const double* euler, int R, double* score,
+                          double* grad, double* hess) {
+  const int L = band.L;
+  switch (W) {
+    case 16: launch_correlate_w<16, HESS>(p, grid, s, band, X, L, euler, R, score, grad, hess); break;
+    case 12: launch_correlate_w<12, HESS>(p, grid, s, band, X, L, euler, R, score, grad, hess); break;
+    case 10: launch_correlate_w<10, HESS>(p, grid, s, band, X, L, euler, R, score, grad, hess); break;
+    case 8: launch_correlate_w<8, HESS>(p, grid, s, band, X, L, euler, R, score, grad, hess); break;
+    case 6: launch_correlate_w<6, HESS>(p, grid, s, band, X, L, euler, R, score, grad, hess); break;
+    case 5: launch_correlate_w<5, HESS>(p, grid, s, band, X, L, euler, R, score, grad, hess); break;
+    default: launch_correlate_w<4, HESS>(p, grid, s, band, X, L, euler, R, score, grad, hess); break;
+  }
+}
+
+template <int W, bool NEWTON>
 void launch_march_w(bh_plan* p, dim3 grid, hipStream_t s, const DevBand& band, const double* X,
-                    int L, const double* Wb, int P, const bh_align_opts& o, double* state,
+                    const double* Wb, int P, int steps, const bh_align_opts& o, double* state,
                     double* sscore) {
-  ProfScope ps(p, "march_L" + std::to_string(L), s,
-               (int64_t)grid.y * P * (o.steps_per_band + 1) * band.n_entries);
-  hipLaunchKernelGGL(k_march<W>, grid, dim3(64 * W), 0, s, band.p_first,
-                     band.wave_p + wave_block_offset(L, W), band.rec, X,
-                     band.n_entries, L, Wb, P, o.steps_per_band, o.step_init, o.step_grow,
-                     o.step_shrink, state, sscore);
+  const int L = band.L;
+  ProfScope ps(p, (NEWTON ? "newton_L" : "march_L") + std::to_string(L), s,
+               (int64_t)grid.y * P * (steps + 1) * band.n_entries);
+  hipLaunchKernelGGL((k_march<W, NEWTON>), grid, dim3(64 * W), 0, s, band.p_first,
+                     band.wave_p + wave_block_offset(L, W), band.rec, X, band.n_entries, L, Wb, P,
+                     steps, o.step_init, o.step_grow, o.step_shrink, state, sscore);
+}
+
+template <bool NEWTON>
+void launch_march_any(int W, bh_plan* p, dim3 grid, hipStream_t s, const DevBand& band,
+                      const double* X, const double* Wb, int P, int steps,
+                      const bh_align_opts& o, double* state, double* sscore) {
+  switch (W) {
+    case 16: launch_march_w<16, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
+    case 12: launch_march_w<12, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
+    case 10: launch_march_w<10, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
+    case 8: launch_march_w<8, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
+    case 6: launch_march_w<6, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
+    case 5: launch_march_w<5, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
+    default: launch_march_w<4, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
+  }
 }
 
 int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b,
@@ -406,35 +642,43 @@ int launch_cross_power_dense(bh_plan* p, const DevBand& band, const float* a, co
   return BH_OK;
 }
 
+int launch_degree_energy(bh_plan* p, const DevBand& band, const float* a, const float* b,
+                         const int32_t* tmpl, int n_tmpl, int64_t B, double* energy,
+                         hipStream_t s) {
+  ProfScope ps(p, "degree_energy", s, B);
+  hipLaunchKernelGGL(k_degree_energy, dim3((unsigned)B), dim3(256), 0, s, a, b, p->C, tmpl, n_tmpl,
+                     band.L, band.deg_start, band.deg_off, energy);
+  BH_HIP(hipGetLastError());
+  return BH_OK;
+}
+
 int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const float* b, int64_t B,
-                     const double* euler, int R, double* score, double* grad, hipStream_t s) {
+                     const double* euler, int R, double* score, double* grad, double* hess,
+                     hipStream_t s) {
   double* X = nullptr;
   int rc = prepare_band(p, band, a, b, nullptr, 1, B, &X, s);
   if (rc != BH_OK) return rc;
   const int64_t chunks = (R + 63) / 64;
   const dim3 grid((unsigned)chunks, (unsigned)B);
   const int W = pick_waves(chunks * B, band.L);
-  switch (W) {
-    case 16: launch_correlate_w<16>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
-    case 12: launch_correlate_w<12>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
-    case 10: launch_correlate_w<10>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
-    case 8: launch_correlate_w<8>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
-    case 6: launch_correlate_w<6>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
-    case 5: launch_correlate_w<5>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
-    default: launch_correlate_w<4>(p, grid, s, band, X, band.L, euler, R, score, grad); break;
-  }
+  if (hess)
+    launch_correlate_any<true>(W, p, grid, s, band, X, euler, R, score, grad, hess);
+  else
+    launch_correlate_any<false>(W, p, grid, s, band, X, euler, R, score, grad, nullptr);
   BH_HIP(hipGetLastError());
   return BH_OK;
 }
 
 int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl, int n_tmpl,
-                 int64_t B, const bh_align_opts& o,
-                 const double* starts, double* euler_out, double* score_out, double* all_euler,
-                 double* all_score, hipStream_t s) {
-  const int P = o.n_restarts;
+                 int64_t B, const bh_align_opts& o, const double* starts, double* euler_out,
+                 double* score_out, double* all_euler, double* all_score, hipStream_t s) {
+  int P = o.n_restarts;
+  const bool prune = o.n_keep > 0 && o.n_keep < P;
+  const int K = prune ? o.n_keep : P;
   int rc;
   if ((rc = grow(p->state_scr, (size_t)B * P * 4 * sizeof(double))) != BH_OK) return rc;
   if ((rc = grow(p->misc_scr, (size_t)B * sizeof(double))) != BH_OK) return rc;
+  if (prune && (rc = grow(p->prune_scr, (size_t)B * K * 4 * sizeof(double))) != BH_OK) return rc;
   double* state = (double*)p->state_scr.ptr;
   double* sscore = state + (size_t)B * P * 3;
   double* Wb = (double*)p->misc_scr.ptr;
@@ -447,34 +691,48 @@ int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl
     if ((rc = get_band(p, o.bands[i], &band)) != BH_OK) return rc;
     bands.push_back(band);
   }
-  const int64_t chunks = (P + 63) / 64;
-  const dim3 grid((unsigned)chunks, (unsigned)B);
-  for (const DevBand* band : bands) {
+  for (int bi = 0; bi < o.n_bands; ++bi) {
+    const DevBand* band = bands[bi];
     double* X = nullptr;
     if ((rc = prepare_band(p, *band, a, b, tmpl, n_tmpl, B, &X, s)) != BH_OK) return rc;
     {
       ProfScope ps(p, "band_weight", s, B);
       hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, b, p->C, tmpl,
-                         n_tmpl, band->L,
-                         band->deg_start, band->deg_off, Wb);
+                         n_tmpl, band->L, band->deg_start, band->deg_off, Wb);
     }
     BH_HIP(hipGetLastError());
+    const int64_t chunks = (P + 63) / 64;
+    const dim3 grid((unsigned)chunks, (unsigned)B);
     const int W = pick_waves(chunks * B, band->L, o.batch_invariant != 0);
-    switch (W) {
-      case 16: launch_march_w<16>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
-      case 12: launch_march_w<12>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
-      case 10: launch_march_w<10>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
-      case 8: launch_march_w<8>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
-      case 6: launch_march_w<6>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
-      case 5: launch_march_w<5>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
-      default: launch_march_w<4>(p, grid, s, *band, X, band->L, Wb, P, o, state, sscore); break;
+    const bool newton = bi >= o.n_bands - o.newton_bands;
+    if (newton) {
+      const int steps = o.newton_steps > 0 ? o.newton_steps : o.steps_per_band;
+      launch_march_any<true>(W, p, grid, s, *band, X, Wb, P, steps, o, state, sscore);
+    } else {
+      launch_march_any<false>(W, p, grid, s, *band, X, Wb, P, o.steps_per_band, o, state,
+                              sscore);
     }
     BH_HIP(hipGetLastError());
+    if (bi == 0 && prune) {
+      double* kst = (double*)p->prune_scr.ptr;
+      double* ksc = kst + (size_t)B * K * 3;
+      const double half = 0.5 * o.keep_min_sep;
+      const double thr = 4.0 * sin(half) * sin(half);
+      {
+        ProfScope ps(p, "prune", s, B);
+        hipLaunchKernelGGL(k_prune, dim3((unsigned)B), dim3(64), 0, s, state, sscore, P, K, thr,
+                           kst, ksc);
+      }
+      BH_HIP(hipGetLastError());
+      state = kst;
+      sscore = ksc;
+      P = K;
+    }
   }
   {
-  ProfScope ps(p, "select", s, B);
-  hipLaunchKernelGGL(k_select, dim3((unsigned)B), dim3(64), 0, s, state, sscore, P, euler_out,
-                     score_out);
+    ProfScope ps(p, "select", s, B);
+    hipLaunchKernelGGL(k_select, dim3((unsigned)B), dim3(64), 0, s, state, sscore, P, euler_out,
+                       score_out);
   }
   BH_HIP(hipGetLastError());
   if (all_euler)

@@ -63,6 +63,12 @@ def test_error_codes():
     # calls on a NULL plan
     assert L.bh_expand(None, None, 1, None, None) == _lib.BH_EINVAL
     assert L.bh_plan_num_coeffs(None, 0) == _lib.BH_EINVAL
+    assert L.bh_expand_ex(None, None, 1, 0, None, None, None) == _lib.BH_EINVAL
+    assert L.bh_correlate_hess(None, None, None, 1, 0, None, 1, None, None, None, None) == _lib.BH_EINVAL
+    assert L.bh_degree_energy(None, None, None, 1, 0, None, None) == _lib.BH_EINVAL
+    o = _lib.AlignOpts()
+    assert L.bh_align_t(None, None, None, 1, None, 1, ctypes.byref(o), None, None, None, None,
+                        None, None) == _lib.BH_EINVAL
     L.bh_plan_destroy(None)   # accepted
     with pytest.raises(_lib.BhError):
         api.index_size(-3)
