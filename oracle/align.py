@@ -188,3 +188,18 @@ def align_batch(A, b, idx: IndexSet, bands, starts, steps: int, **kw):
         eu[i] = r["euler"][r["best"]]
         s[i] = r["score"][r["best"]]
     return eu, s
+
+
+def align_shifts(vol, b, idx: IndexSet, shifts, bands, starts, steps: int, **kw):
+    """Shift search for one particle: for each integer voxel shift d, expand
+    the shifted volume f(x + d h) and march from `starts`; the best final
+    score wins (first shift on ties).  Returns (euler, score, shift index)."""
+    from . import expand
+    best = None
+    for si, d in enumerate(shifts):
+        a = expand.expand(expand.shift_volume(np.asarray(vol, dtype=np.float64), d), idx)
+        r = march(a, b, idx, bands, starts, steps, **kw)
+        s = r["score"][r["best"]]
+        if best is None or s > best[1]:
+            best = (r["euler"][r["best"]], s, si)
+    return best

@@ -66,3 +66,14 @@ def real_symmetric(coeffs: np.ndarray, idx: IndexSet) -> np.ndarray:
         ms = np.arange(-l, l + 1)
         sym[..., off:off + 2 * l + 1] = ((-1.0) ** ms) * np.conj(blk[..., ::-1])
     return 0.5 * (out + sym)
+
+
+def shift_volume(f: np.ndarray, d) -> np.ndarray:
+    """f_s[i, j, k] = f[i + dx, j + dy, k + dz] (zero outside the box): the
+    sampled f(x + s) for the voxel shift s = d h (Sec. II-C, shift grid)."""
+    N = f.shape[0]
+    out = np.zeros_like(f)
+    src = [slice(max(0, di), min(N, N + di)) for di in d]
+    dst = [slice(max(0, -di), min(N, N - di)) for di in d]
+    out[dst[0], dst[1], dst[2]] = f[src[0], src[1], src[2]]
+    return out
