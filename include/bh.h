@@ -247,6 +247,27 @@ int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templat
                double* all_euler, double* all_score, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Shift search (Sec. II-C: Eq. (2) maximised for each shift of a grid,
+ * then the best shift kept).  For each particle b and each integer voxel
+ * shift s = (dx, dy, dz) of the table, the shifted volume
+ *   f_s[i][j][k] = f_b[i + dx][j + dy][k + dz]   (0 outside the box),
+ * i.e. f_s(x) = f(x + s h), is expanded (FP32, as bh_expand) and aligned
+ * with `opts` from the particle's starts; the shift with the highest final
+ * score wins (lowest table index on ties).
+ * vols:      dev float[B][N][N][N]
+ * shifts:    host int32[S][3], 1 <= S <= 125, |d| <= N (read during the call)
+ * b:         dev float[C(L_max)][2] template coefficients
+ * starts:    dev double[B][n_restarts][3] (used for every shift)
+ * euler_out: dev double[B][3], score_out: dev double[B],
+ * shift_out: dev int32[B] index into `shifts`.
+ * Device scratch grows to about B*S*(8 C + 24 n_restarts) bytes plus the
+ * expansion and march buffers of B*S particles.
+ * ------------------------------------------------------------------- */
+int bh_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shifts, int S,
+                    const float* b, const bh_align_opts* opts, const double* starts,
+                    double* euler_out, double* score_out, int32_t* shift_out, void* stream);
+
+/* ---------------------------------------------------------------------
  * Per-kernel timing (for measurement; off by default).
  * bh_profile_enable(p, 1) synchronises the device, clears earlier records
  * and starts recording a pair of HIP events on the call's stream around

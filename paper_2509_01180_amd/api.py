@@ -243,6 +243,31 @@ class Plan:
             return eu, sc, ae, asc
         return eu, sc
 
+    def align_shifts(self, vols: torch.Tensor, b: torch.Tensor, shifts, bands: Sequence[int],
+                     starts: torch.Tensor, steps: int, step_init: float = 1.0,
+                     step_grow: float = 1.25, step_shrink: float = 0.5, newton_bands: int = 0,
+                     newton_steps: int = 0, keep: int = 0, min_sep: float = 0.0):
+        """Shift search: (euler [B, 3], score [B], shift index [B]) over the
+        integer voxel shifts (sequence of (dx, dy, dz)); see bh_align_shifts."""
+        import numpy as np
+        B = vols.shape[0]
+        P = starts.shape[1]
+        _dev(vols, torch.float32, (B, self.N, self.N, self.N), "vols")
+        _dev(b, torch.float32, (self.C, 2), "b")
+        _dev(starts, torch.float64, (B, P, 3), "starts")
+        sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.int32).reshape(-1, 3))
+        bl = (ctypes.c_int32 * len(bands))(*[int(x) for x in bands])
+        o = AlignOpts(ctypes.cast(bl, ctypes.POINTER(ctypes.c_int32)), len(bands), int(steps), P,
+                      float(step_init), float(step_grow), float(step_shrink), 0,
+                      int(newton_bands), int(newton_steps), int(keep), float(min_sep))
+        eu = torch.empty((B, 3), dtype=torch.float64, device=vols.device)
+        sc = torch.empty((B,), dtype=torch.float64, device=vols.device)
+        si = torch.empty((B,), dtype=torch.int32, device=vols.device)
+        check(lib().bh_align_shifts(self._h, _ptr(vols), B, sh.ctypes.data_as(ctypes.c_void_p),
+                                    len(sh), _ptr(b), ctypes.byref(o), _ptr(starts), _ptr(eu),
+                                    _ptr(sc), _ptr(si), _stream()), "bh_align_shifts")
+        return eu, sc, si
+
     def align_t(self, a: torch.Tensor, templates: torch.Tensor, tmpl_idx: torch.Tensor | None,
                 bands: Sequence[int], starts: torch.Tensor, steps: int, step_init: float = 1.0,
                 step_grow: float = 1.25, step_shrink: float = 0.5, return_all: bool = False,

@@ -253,7 +253,7 @@ void bh_plan_destroy(bh_plan* p) {
                   (void*)p->csgn})
     if (q) (void)hipFree(q);
   for (Buffer* b : {&p->gathered, &p->partial, &p->xi_scr, &p->state_scr, &p->misc_scr,
-                    &p->prune_scr})
+                    &p->prune_scr, &p->shift_scr})
     if (b->ptr) (void)hipFree(b->ptr);
   for (auto& kv : p->bands) free_band(kv.second);
   p->prof.destroy();
@@ -405,15 +405,7 @@ int bh_degree_energy(bh_plan* p, const float* a, const float* b, int64_t B, int 
   });
 }
 
-int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templates,
-               const int32_t* tmpl_idx, int64_t B, const bh_align_opts* o, const double* starts,
-               double* euler_out, double* score_out, double* all_euler, double* all_score,
-               void* stream) {
-  if (!p) return set_error(BH_EINVAL, "plan is NULL");
-  if (!o) return set_error(BH_EINVAL, "opts is NULL");
-  if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
-  if (n_templates < 1 || n_templates > (1 << 20)) return set_error(BH_EINVAL, "bad template count");
-  if (n_templates > 1 && !tmpl_idx) return set_error(BH_EINVAL, "template index table is NULL");
+static int check_align_opts(const bh_plan* p, const bh_align_opts* o) {
   if (o->n_bands < 1 || o->n_bands > 16 || !o->bands) return set_error(BH_EINVAL, "bad band list");
   for (int i = 0; i < o->n_bands; ++i)
     if (o->bands[i] < 0 || o->bands[i] > p->L_max) return set_error(BH_EINVAL, "band outside 0..L_max");
@@ -429,6 +421,20 @@ int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templat
     return set_error(BH_EUNSUPPORTED, "candidate pruning needs n_restarts <= 1024");
   if (!(o->keep_min_sep >= 0.0) || o->keep_min_sep > 3.141592653589793)
     return set_error(BH_EINVAL, "keep_min_sep outside [0, pi]");
+  return BH_OK;
+}
+
+int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templates,
+               const int32_t* tmpl_idx, int64_t B, const bh_align_opts* o, const double* starts,
+               double* euler_out, double* score_out, double* all_euler, double* all_score,
+               void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (!o) return set_error(BH_EINVAL, "opts is NULL");
+  if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
+  if (n_templates < 1 || n_templates > (1 << 20)) return set_error(BH_EINVAL, "bad template count");
+  if (n_templates > 1 && !tmpl_idx) return set_error(BH_EINVAL, "template index table is NULL");
+  int rc = check_align_opts(p, o);
+  if (rc != BH_OK) return rc;
   if (B == 0) return BH_OK;
   if (!a || !templates || !starts || !euler_out || !score_out) return set_error(BH_EINVAL, "NULL buffer");
   return guarded([&]() -> int {
@@ -436,6 +442,29 @@ int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templat
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
     return launch_align(p, a, templates, n_templates > 1 ? tmpl_idx : nullptr, n_templates, B, *o,
                         starts, euler_out, score_out, all_euler, all_score, (hipStream_t)stream);
+  });
+}
+
+int bh_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shifts, int S,
+                    const float* b, const bh_align_opts* o, const double* starts,
+                    double* euler_out, double* score_out, int32_t* shift_out, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (!o) return set_error(BH_EINVAL, "opts is NULL");
+  if (S < 1 || S > kMaxShifts) return set_error(BH_EINVAL, "shift count outside 1..125");
+  if (!shifts) return set_error(BH_EINVAL, "shift table is NULL");
+  for (int i = 0; i < 3 * S; ++i)
+    if (shifts[i] < -p->N || shifts[i] > p->N) return set_error(BH_EINVAL, "shift beyond the box");
+  if (B < 0 || B * (int64_t)S > (1LL << 21)) return set_error(BH_EINVAL, "batch size out of range");
+  if (B == 0) return BH_OK;
+  if (!vols || !b || !starts || !euler_out || !score_out || !shift_out)
+    return set_error(BH_EINVAL, "NULL buffer");
+  int rc = check_align_opts(p, o);
+  if (rc != BH_OK) return rc;
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    return launch_align_shifts(p, vols, B, shifts, S, b, *o, starts, euler_out, score_out,
+                               shift_out, (hipStream_t)stream);
   });
 }
 

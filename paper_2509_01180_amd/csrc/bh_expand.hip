@@ -39,6 +39,42 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ vols, 
   }
 }
 
+// As k_gather for rows r = b * S + s of integer-shifted volumes:
+// Ft[v][r] = f_b at the ball voxel (i, j, k) moved by shift s, i.e.
+// vols[b][i + dx][j + dy][k + dz] (0 where that leaves the box).
+__global__ __launch_bounds__(256) void k_gather_shift(const float* __restrict__ vols, int N,
+                                                      int64_t rows, int S, ShiftTable shifts,
+                                                      const int32_t* __restrict__ vidx, int64_t V,
+                                                      int64_t M_pad, float* __restrict__ Ft) {
+  __shared__ float tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  const int64_t v0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+  const int64_t v = v0 + tx;
+  const int32_t lin = (v < V) ? vidx[v] : 0;
+  const int vi = lin / (N * N), vj = (lin / N) % N, vk = lin % N;
+  const int64_t vol_stride = (int64_t)N * N * N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = r0 + ty + 8 * i;
+    float val = 0.0f;
+    if (v < V && r < rows) {
+      const int64_t b = r / S;
+      const int sh = (int)(r % S);
+      const int si = vi + shifts.d[sh][0], sj = vj + shifts.d[sh][1],
+                sk = vk + shifts.d[sh][2];
+      if (si >= 0 && si < N && sj >= 0 && sj < N && sk >= 0 && sk < N)
+        val = vols[b * vol_stride + ((int64_t)si * N + sj) * N + sk];
+    }
+    tile[ty + 8 * i][tx] = val;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t vv = v0 + ty + 8 * i;
+    Ft[vv * M_pad + r0 + tx] = tile[tx][ty + 8 * i];
+  }
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (linear id mod 8),
 // each with its own L2.  When the coefficient tiles divide evenly, XCD x
 // takes coefficient tiles [x*nt/8, (x+1)*nt/8) for every particle tile and
@@ -166,7 +202,8 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ part, 
 }  // namespace
 
 int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s,
-                  bool batch_invariant) {
+                  bool batch_invariant, const ShiftTable* shifts, int S) {
+  if (shifts) B *= S;   // one GEMM row per (particle, shift)
   if (B == 0) return BH_OK;
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
   const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
@@ -179,10 +216,14 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
   float* Ft = (float*)p->gathered.ptr;
   float* part = (float*)p->partial.ptr;
   const int64_t vol_stride = (int64_t)p->N * p->N * p->N;
-  {
-  ProfScope ps(p, "gather", s, B);
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)(p->V_pad / 32), (unsigned)(M_pad / 32)), dim3(256), 0,
-                     s, vols, vol_stride, B, p->vidx, p->V, M_pad, Ft);
+  if (shifts) {
+    ProfScope ps(p, "gather_shift", s, B);
+    hipLaunchKernelGGL(k_gather_shift, dim3((unsigned)(p->V_pad / 32), (unsigned)(M_pad / 32)),
+                       dim3(256), 0, s, vols, p->N, B, S, *shifts, p->vidx, p->V, M_pad, Ft);
+  } else {
+    ProfScope ps(p, "gather", s, B);
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)(p->V_pad / 32), (unsigned)(M_pad / 32)),
+                       dim3(256), 0, s, vols, vol_stride, B, p->vidx, p->V, M_pad, Ft);
   }
   BH_HIP(hipGetLastError());
   {

@@ -90,7 +90,7 @@ struct bh_plan {
   float* csgn = nullptr;         // [C][2] sign applied to it
   std::vector<int64_t> band_size;   // C(L) for L = 0..L_max
   // scratch (grown on demand, owned by the plan)
-  bh::Buffer gathered, partial, xi_scr, state_scr, misc_scr, prune_scr;
+  bh::Buffer gathered, partial, xi_scr, state_scr, misc_scr, prune_scr, shift_scr;
   std::map<int, bh::DevBand> bands;
   bh::Profiler prof;
 };
@@ -127,8 +127,15 @@ inline int expand_split(int64_t mt, int64_t nt, int64_t nk_total, bool batch_inv
   while (nsplit < 16 && mt * nt * nsplit < 1024 && (nk_total / (nsplit * 2)) >= 8) nsplit *= 2;
   return nsplit;
 }
+// Integer voxel shifts, passed to kernels by value.
+constexpr int kMaxShifts = 125;
+struct ShiftTable {
+  int32_t d[kMaxShifts][3];
+};
+// With `shifts` the rows are the B*S shifted volumes (particle-major) of
+// the S integer voxel shifts.
 int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s,
-                  bool batch_invariant = false);
+                  bool batch_invariant = false, const ShiftTable* shifts = nullptr, int S = 1);
 int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, float* coeffs,
                        float* coarse_out, hipStream_t s, bool batch_invariant = false);
 int launch_cross_power_dense(bh_plan* p, const DevBand& band, const float* a, const float* b,
@@ -139,6 +146,9 @@ int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const floa
 int launch_degree_energy(bh_plan* p, const DevBand& band, const float* a, const float* b,
                          const int32_t* tmpl, int n_tmpl, int64_t B, double* energy,
                          hipStream_t s);
+int launch_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shifts_host,
+                        int S, const float* b, const bh_align_opts& o, const double* starts,
+                        double* euler_out, double* score_out, int32_t* shift_out, hipStream_t s);
 int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl, int n_tmpl,
                  int64_t B, const bh_align_opts& o,
                  const double* starts, double* euler_out, double* score_out, double* all_euler,

@@ -548,6 +548,39 @@ __global__ __launch_bounds__(256) void k_degree_energy(
   }
 }
 
+// starts of particle b for each of its S shifted copies: out[b*S + s] = in[b].
+__global__ void k_repeat_starts(const double* __restrict__ in, int64_t B, int S, int P,
+                                double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)P * 3;
+  if (t >= B * S * per) return;
+  const int64_t row = t / per, k = t % per;
+  out[t] = in[(row / S) * per + k];
+}
+
+// Best shift per particle: highest score over its S rows (lowest shift
+// index on ties).
+__global__ void k_select_shift(const double* __restrict__ eu, const double* __restrict__ sc,
+                               int64_t B, int S, double* __restrict__ euler_out,
+                               double* __restrict__ score_out, int32_t* __restrict__ shift_out) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  int best = 0;
+  double bs = sc[b * S];
+  for (int s = 1; s < S; ++s) {
+    const double v = sc[b * S + s];
+    if (v > bs || (isnan(bs) && !isnan(v))) {
+      bs = v;
+      best = s;
+    }
+  }
+  euler_out[b * 3 + 0] = eu[(b * S + best) * 3 + 0];
+  euler_out[b * 3 + 1] = eu[(b * S + best) * 3 + 1];
+  euler_out[b * 3 + 2] = eu[(b * S + best) * 3 + 2];
+  score_out[b] = bs;
+  shift_out[b] = best;
+}
+
 int pick_waves(int64_t groups, int L, bool batch_invariant = false) {
   if (BH_SCORE_FIXED_W > 0) return BH_SCORE_FIXED_W;
   // Measured on MI355X (1000 particles x 64 restarts, bands 8..32): 12 waves
@@ -741,6 +774,42 @@ int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl
   if (all_score)
     BH_HIP(hipMemcpyAsync(all_score, sscore, (size_t)B * P * sizeof(double),
                           hipMemcpyDeviceToDevice, s));
+  return BH_OK;
+}
+
+int launch_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shifts_host,
+                        int S, const float* b, const bh_align_opts& o, const double* starts,
+                        double* euler_out, double* score_out, int32_t* shift_out,
+                        hipStream_t s) {
+  const int64_t rows = B * S;
+  const int P = o.n_restarts;
+  // scratch: coefficients [rows][C][2] | starts [rows][P][3] | best per row
+  ShiftTable tab = {};
+  for (int i = 0; i < S; ++i)
+    for (int k = 0; k < 3; ++k) tab.d[i][k] = shifts_host[3 * i + k];
+  const size_t sh_bytes = 0;
+  const size_t co_bytes = ((size_t)rows * p->C * 2 * sizeof(float) + 255) / 256 * 256;
+  const size_t st_bytes = (size_t)rows * P * 3 * sizeof(double);
+  const size_t eu_bytes = (size_t)rows * 3 * sizeof(double);
+  const size_t sc_bytes = (size_t)rows * sizeof(double);
+  int rc = grow(p->shift_scr, sh_bytes + co_bytes + st_bytes + eu_bytes + sc_bytes);
+  if (rc != BH_OK) return rc;
+  char* base = (char*)p->shift_scr.ptr;
+  float* coeffs = (float*)(base + sh_bytes);
+  double* st = (double*)(base + sh_bytes + co_bytes);
+  double* eu = (double*)(base + sh_bytes + co_bytes + st_bytes);
+  double* sc = (double*)(base + sh_bytes + co_bytes + st_bytes + eu_bytes);
+  if ((rc = launch_expand(p, vols, B, coeffs, s, false, &tab, S)) != BH_OK) return rc;
+  const int64_t n = rows * P * 3;
+  hipLaunchKernelGGL(k_repeat_starts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, starts,
+                     B, S, P, st);
+  BH_HIP(hipGetLastError());
+  if ((rc = launch_align(p, coeffs, b, nullptr, 1, rows, o, st, eu, sc, nullptr, nullptr, s)) !=
+      BH_OK)
+    return rc;
+  hipLaunchKernelGGL(k_select_shift, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, eu, sc, B,
+                     S, euler_out, score_out, shift_out);
+  BH_HIP(hipGetLastError());
   return BH_OK;
 }
 
