@@ -50,9 +50,14 @@ constexpr double kSin2Floor = 1e-6;
 #else
 #define BH_SCORE_OCCUPANCY
 #endif
-// The Hessian evaluators carry four more chain sums and a longer epilogue;
-// they are given up to 128 registers (4 waves per SIMD) instead.
+// The Hessian evaluators (four more chain sums, a longer epilogue) and the
+// packed march (weights in vector registers) are given up to 128 registers
+// (4 waves per SIMD) instead.
+// Both together get up to 168 (3 waves per SIMD).
 #define BH_HESS_OCCUPANCY(H) __attribute__((amdgpu_waves_per_eu((H) ? 4 : BH_SCORE_WAVES_PER_EU)))
+#define BH_MARCH_OCCUPANCY(NEWTON, PACKED)                                              \
+  __attribute__((amdgpu_waves_per_eu(((NEWTON) && (PACKED)) ? 3                          \
+                                     : (((NEWTON) || (PACKED)) ? 4 : BH_SCORE_WAVES_PER_EU))))
 
 // ------------------------------------------------------------ cross-power --
 
@@ -292,11 +297,16 @@ enum {
   ST_HAA, ST_HAB, ST_HAG, ST_HBB, ST_HBG, ST_HGG, ST_ETA0, ST_N
 };
 
-template <int W, bool NEWTON>
-__global__ __launch_bounds__(64 * W) BH_HESS_OCCUPANCY(NEWTON) void k_march(
+//
+// G < 64 packs 64 / G particles into a workgroup, G lanes (restarts) each
+// (P <= G): the restarts that survive candidate pruning fill the waves.
+// The weights X then differ between lane groups and are read with vector
+// loads; the recurrence tables stay wave-uniform.
+template <int W, bool NEWTON, int G>
+__global__ __launch_bounds__(64 * W) BH_MARCH_OCCUPANCY(NEWTON, G < 64) void k_march(
     const int32_t* __restrict__ p_first, const int32_t* __restrict__ wave_p,
     const double* __restrict__ rec, const double* __restrict__ X, int64_t n_entries, int L,
-    const double* __restrict__ Wb, int P, int steps, double step_init, double grow,
+    const double* __restrict__ Wb, int64_t B, int P, int steps, double step_init, double grow,
     double shrink, double* __restrict__ state, double* __restrict__ sscore) {
   constexpr int NV = NEWTON ? 10 : 4;
   constexpr int NS = NEWTON ? ST_N : ST_HAA;
@@ -304,9 +314,16 @@ __global__ __launch_bounds__(64 * W) BH_HESS_OCCUPANCY(NEWTON) void k_march(
   __shared__ double st[NS * 64];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t pb = blockIdx.y;
-  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
-  const bool active = r < P;
+  int64_t pb, r;
+  if constexpr (G == 64) {
+    pb = blockIdx.y;
+    r = (int64_t)blockIdx.x * 64 + lane;
+  } else {
+    pb = (int64_t)blockIdx.y * (64 / G) + lane / G;
+    r = lane % G;
+  }
+  const bool active = pb < B && r < P;
+  if (pb >= B) pb = B - 1;          // idle lanes read a valid particle
   const double* Xp = X + pb * n_entries * 4;
   const double wb = Wb[pb];
   const double eta0 = (wb > 0.0) ? step_init / wb : 0.0;
@@ -621,30 +638,51 @@ void launch_correlate_any(int W, bh_plan* p, dim3 grid, hipStream_t s, const Dev
   }
 }
 
-template <int W, bool NEWTON>
-void launch_march_w(bh_plan* p, dim3 grid, hipStream_t s, const DevBand& band, const double* X,
+template <int W, bool NEWTON, int G>
+void launch_march_w(bh_plan* p, int64_t B, hipStream_t s, const DevBand& band, const double* X,
                     const double* Wb, int P, int steps, const bh_align_opts& o, double* state,
                     double* sscore) {
   const int L = band.L;
+  const dim3 grid = (G == 64) ? dim3((unsigned)((P + 63) / 64), (unsigned)B)
+                              : dim3(1u, (unsigned)((B + 64 / G - 1) / (64 / G)));
   ProfScope ps(p, (NEWTON ? "newton_L" : "march_L") + std::to_string(L), s,
-               (int64_t)grid.y * P * (steps + 1) * band.n_entries);
-  hipLaunchKernelGGL((k_march<W, NEWTON>), grid, dim3(64 * W), 0, s, band.p_first,
-                     band.wave_p + wave_block_offset(L, W), band.rec, X, band.n_entries, L, Wb, P,
-                     steps, o.step_init, o.step_grow, o.step_shrink, state, sscore);
+               B * P * (int64_t)(steps + 1) * band.n_entries);
+  hipLaunchKernelGGL((k_march<W, NEWTON, G>), grid, dim3(64 * W), 0, s, band.p_first,
+                     band.wave_p + wave_block_offset(L, W), band.rec, X, band.n_entries, L, Wb, B,
+                     P, steps, o.step_init, o.step_grow, o.step_shrink, state, sscore);
 }
 
+// G: lanes per particle (64, or 32 / 16 / 8 when P <= G, packed).
 template <bool NEWTON>
-void launch_march_any(int W, bh_plan* p, dim3 grid, hipStream_t s, const DevBand& band,
+void launch_march_any(int W, int G, bh_plan* p, int64_t B, hipStream_t s, const DevBand& band,
                       const double* X, const double* Wb, int P, int steps,
                       const bh_align_opts& o, double* state, double* sscore) {
+  if (G < 64) {
+    // packed launches use 12 waves (4 for bands up to 8)
+    const bool small = W <= 6;
+#define BH_PACKED(GG)                                                                         \
+  if (small)                                                                                  \
+    launch_march_w<4, NEWTON, GG>(p, B, s, band, X, Wb, P, steps, o, state, sscore);          \
+  else                                                                                        \
+    launch_march_w<12, NEWTON, GG>(p, B, s, band, X, Wb, P, steps, o, state, sscore);
+    if (G == 8) {
+      BH_PACKED(8)
+    } else if (G == 16) {
+      BH_PACKED(16)
+    } else {
+      BH_PACKED(32)
+    }
+#undef BH_PACKED
+    return;
+  }
   switch (W) {
-    case 16: launch_march_w<16, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
-    case 12: launch_march_w<12, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
-    case 10: launch_march_w<10, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
-    case 8: launch_march_w<8, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
-    case 6: launch_march_w<6, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
-    case 5: launch_march_w<5, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
-    default: launch_march_w<4, NEWTON>(p, grid, s, band, X, Wb, P, steps, o, state, sscore); break;
+    case 16: launch_march_w<16, NEWTON, 64>(p, B, s, band, X, Wb, P, steps, o, state, sscore); break;
+    case 12: launch_march_w<12, NEWTON, 64>(p, B, s, band, X, Wb, P, steps, o, state, sscore); break;
+    case 10: launch_march_w<10, NEWTON, 64>(p, B, s, band, X, Wb, P, steps, o, state, sscore); break;
+    case 8: launch_march_w<8, NEWTON, 64>(p, B, s, band, X, Wb, P, steps, o, state, sscore); break;
+    case 6: launch_march_w<6, NEWTON, 64>(p, B, s, band, X, Wb, P, steps, o, state, sscore); break;
+    case 5: launch_march_w<5, NEWTON, 64>(p, B, s, band, X, Wb, P, steps, o, state, sscore); break;
+    default: launch_march_w<4, NEWTON, 64>(p, B, s, band, X, Wb, P, steps, o, state, sscore); break;
   }
 }
 
@@ -734,15 +772,16 @@ int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl
                          n_tmpl, band->L, band->deg_start, band->deg_off, Wb);
     }
     BH_HIP(hipGetLastError());
-    const int64_t chunks = (P + 63) / 64;
-    const dim3 grid((unsigned)chunks, (unsigned)B);
-    const int W = pick_waves(chunks * B, band->L, o.batch_invariant != 0);
+    // lanes per particle: 64, or fewer when the (pruned) restarts fit
+    const int G = P <= 8 ? 8 : (P <= 16 ? 16 : (P <= 32 ? 32 : 64));
+    const int64_t groups = (G == 64) ? (P + 63) / 64 * B : (B + 64 / G - 1) / (64 / G);
+    const int W = pick_waves(groups, band->L, o.batch_invariant != 0);
     const bool newton = bi >= o.n_bands - o.newton_bands;
     if (newton) {
       const int steps = o.newton_steps > 0 ? o.newton_steps : o.steps_per_band;
-      launch_march_any<true>(W, p, grid, s, *band, X, Wb, P, steps, o, state, sscore);
+      launch_march_any<true>(W, G, p, B, s, *band, X, Wb, P, steps, o, state, sscore);
     } else {
-      launch_march_any<false>(W, p, grid, s, *band, X, Wb, P, o.steps_per_band, o, state,
+      launch_march_any<false>(W, G, p, B, s, *band, X, Wb, P, o.steps_per_band, o, state,
                               sscore);
     }
     BH_HIP(hipGetLastError());
