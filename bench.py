@@ -515,9 +515,10 @@ def serve_bench(args):
         while i < len(reqs) and reqs[i].arrival <= now:
             submitted.append(eng.submit(make_request(reqs[i], t0 + reqs[i].arrival)))
             i += 1
-        if not eng.busy():
+        if not eng.sched.busy():
+            done += eng.step()          # collects finished cohorts, no device work
             nxt = reqs[i].arrival if i < len(reqs) else args.duration
-            time.sleep(max(0.0, min(nxt - now, 0.01)))
+            time.sleep(max(0.0, min(nxt - now, 0.002)))
             continue
         done += eng.step()
         ticks += 1

@@ -236,7 +236,8 @@ class Engine:
         return req
 
     def busy(self) -> bool:
-        return self.sched.busy() or bool(self.pending) or bool(self.ticks_in_flight)
+        """Requests queued, on the device, or finished but not yet collected."""
+        return self.sched.busy() or bool(self.pending)
 
     # -- one tick --
     def step(self) -> list:
@@ -254,6 +255,8 @@ class Engine:
             for r in c.requests:
                 r.admitted = now
             self._start(c)
+        if not self.sched.live:
+            return self._collect()
         for c, band, last in self.sched.plan():
             self._band(c, band, last)
         for c in self.sched.advance():
