@@ -140,6 +140,9 @@ def main():
                     help="paper method: energy-ratio thresholds that pick the bands")
     ap.add_argument("--keep", type=int, default=8, help="paper method: candidates kept")
     ap.add_argument("--newton-steps", type=int, default=6, help="paper method: Newton steps/band")
+    ap.add_argument("--uneven", action="store_true",
+                    help="uneven batch: 20,000 subtomograms of box edges 32/48/64/96 marched together")
+    ap.add_argument("--uneven-total", type=int, default=20000, help="uneven: particles in the batch")
     ap.add_argument("--serving", action="store_true",
                     help="run the serving loop on a Poisson request stream instead")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: requests per second")
@@ -164,6 +167,9 @@ def main():
         return
     if args.method == "paper":
         paper_bench(args)
+        return
+    if args.uneven:
+        uneven_bench(args)
         return
 
     import torch
@@ -424,6 +430,107 @@ def paper_bench(args):
                      "frac_within_1deg_of_plain": round(float(np.mean(d_pp <= 1.0)), 4)},
     }
     plan.close()
+    print(json.dumps(result), flush=True)
+
+
+# ---------------------------------------------------------------- uneven --
+
+def uneven_bench(args):
+    """Uneven batch: equal shares of box edges 32/48/64/96 (L = 16/24/32/40,
+    bands every 8 up to each L), 4 templates, wedge and SNR drawn per
+    particle; one step = the four expansions + one march over all particles
+    (one launch per band).  The same work as four separate per-box calls is
+    timed beside it.  Prints one JSON line."""
+    import torch
+    import synth.uneven as su
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd.uneven import Group, UnevenAligner
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    P, T = 64, 20
+    boxes = sorted(su.BOX_BANDLIMIT)
+    blobs = su.uneven_templates()
+    per_box = args.uneven_total // len(boxes)
+    pool = 32
+    t_gen = time.perf_counter()
+    pools, truths = {}, {}
+    with ThreadPoolExecutor(max(1, args.threads)) as ex:
+        for N in boxes:
+            jobs = [(t, j) for t in range(len(blobs)) for j in range(pool)]
+            out = list(ex.map(lambda tj: su.pool_particle(blobs[tj[0]], N, tj[0], tj[1]), jobs))
+            pools[N] = torch.from_numpy(np.stack([o[0] for o in out])).to(dev)
+            truths[N] = np.stack([o[1] for o in out])
+    rng = np.random.default_rng(4)
+    groups, idx_h = [], {}
+    for N in boxes:
+        idx = rng.integers(0, len(blobs) * pool, per_box)
+        idx_h[N] = idx
+        st = synth.matrix_to_euler_zyz(synth.quat_to_matrix(
+            synth.haar_quaternions(rng, per_box * P))).reshape(per_box, P, 3)
+        groups.append(Group(N, pools[N].index_select(0, torch.from_numpy(idx).to(dev)),
+                            (idx // pool).astype(np.int32), torch.from_numpy(st).to(dev)))
+    t_gen = time.perf_counter() - t_gen
+    plans = {N: Plan(N, L, device=0) for N, L in su.BOX_BANDLIMIT.items()}
+    tmpl = {N: plans[N].expand(torch.from_numpy(np.stack(
+        [synth.render_blobs(b, N) for b in blobs]).astype(np.float32)).to(dev)) for N in boxes}
+    ua = UnevenAligner(plans, tmpl, step=8)
+    mode = "fp32" if args.precision == "plain" else "bf16x3"
+    torch.cuda.synchronize()
+    print(f"# {per_box * len(boxes)} particles ready in {t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    def fused():
+        return ua.align(groups, T, mode=mode)
+
+    def separate():
+        out = []
+        for g in groups:
+            plan = plans[g.N]
+            a = plan.expand_ex(g.vols, mode)
+            bands = [b for b in ua.bands if b <= plan.L_max]
+            out.append(plan.align_t(a, tmpl[g.N], torch.from_numpy(g.templates).to(dev), bands,
+                                    g.starts, T))
+        return out
+
+    for _ in range(args.warmup):
+        fused()
+        separate()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = fused()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        separate()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    n_tot = per_box * len(boxes)
+    ms, ms_sep = (t1 - t0) * 1e3 / args.steps, (t2 - t1) * 1e3 / args.steps
+    acc = {}
+    for g, (eu, _sc) in zip(groups, res):
+        R = np.transpose(truths[g.N][idx_h[g.N]], (0, 2, 1))
+        ang = geodesic_deg(eu.cpu().numpy(), synth.matrix_to_euler_zyz(R))
+        acc[str(g.N)] = {"median_deg_vs_planted": round(float(np.median(ang)), 3),
+                         "p90_deg_vs_planted": round(float(np.percentile(ang, 90)), 3)}
+    result = {
+        "metric": "subtomograms aligned/s, uneven batch (box edges 32/48/64/96)",
+        "value": round(n_tot / (ms / 1e3), 1), "unit": "subtomograms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 2),
+        "higher_is_better": True,
+        "dtype": "f32/f64" if mode == "fp32" else "bf16x3 expansion/f64 score",
+        "data": "synthetic",
+        "config": {"workload": f"{n_tot} subtomograms, equal shares of 32^3/48^3/64^3/96^3 "
+                               "(L 16/24/32/40, bands every 8 up to L), 4 templates of 30-80 blobs, "
+                               "wedge +/-U[50,65] deg, SNR U[0.02,0.2], 64 restarts, 20 steps/band",
+                   "bands": ua.bands},
+        "separate_per_box_calls": {"value": round(n_tot / (ms_sep / 1e3), 1),
+                                   "ms_per_step": round(ms_sep, 2)},
+        "accuracy": acc,
+        "setup": {"input_generation_s": round(t_gen, 1)},
+    }
+    for p in plans.values():
+        p.close()
     print(json.dumps(result), flush=True)
 
 

@@ -136,6 +136,12 @@ enum { BH_EXPAND_FP32 = 0, BH_EXPAND_BF16 = 1, BH_EXPAND_BF16X3 = 2,
 int bh_expand_ex(bh_plan* p, const float* vols, int64_t B, int mode, float* coeffs, float* coarse,
                  void* stream);
 
+/* As bh_expand_ex, writing particle b's coefficients at coeffs + 2*b*ldc
+ * (ldc >= C(L_max) complex entries; the rest of each row is left as is), so
+ * particles of several plans can share one coefficient array. */
+int bh_expand_into(bh_plan* p, const float* vols, int64_t B, int mode, float* coeffs, int64_t ldc,
+                   float* coarse, void* stream);
+
 /* ---------------------------------------------------------------------
  * Cross-power of Eq. (2) for band L (0 <= L <= L_max).
  * a:  dev float[B][C(L_max)][2]  particle coefficients
@@ -245,6 +251,25 @@ int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templat
                const int32_t* tmpl_idx, int64_t B, const bh_align_opts* opts,
                const double* starts, double* euler_out, double* score_out,
                double* all_euler, double* all_score, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Uneven batches: particles of different bandlimits (box sizes) marched
+ * together, one launch per band for every particle that takes it.
+ * Band indices are a frequency-ordered prefix, so coefficients of any plan
+ * share the layout of band L; the particle rows (and template rows) are
+ * laid out with a common complex stride lda (ldt) >= C(largest band used).
+ * Lp:       host int32[B], each particle's bandlimit, non-increasing along
+ *           the batch (sort by bandlimit first); particle b takes every band
+ *           of opts->bands (strictly increasing) that is <= Lp[b], and all
+ *           take the first one.
+ * Otherwise as bh_align_t; the band tables come from plan p (L_max >= the
+ * largest band taken).  Newton bands count from the end of opts->bands.
+ * ------------------------------------------------------------------- */
+int bh_align_uneven(bh_plan* p, const float* a, int64_t lda, const int32_t* Lp,
+                    const float* templates, int64_t ldt, int n_templates, const int32_t* tmpl_idx,
+                    int64_t B, const bh_align_opts* opts, const double* starts,
+                    double* euler_out, double* score_out, double* all_euler, double* all_score,
+                    void* stream);
 
 /* ---------------------------------------------------------------------
  * Shift search (Sec. II-C: Eq. (2) maximised for each shift of a grid,

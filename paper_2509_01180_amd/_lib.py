@@ -69,6 +69,9 @@ SIGNATURES = {
     "bh_correlate_hess": (_I, [_P, _P, _P, _I64, _I, _P, _I, _P, _P, _P, _P]),
     "bh_degree_energy": (_I, [_P, _P, _P, _I64, _I, _P, _P]),
     "bh_align_shifts": (_I, [_P, _P, _I64, _P, _I, _P, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P]),
+    "bh_expand_into": (_I, [_P, _P, _I64, _I, _P, _I64, _P, _P]),
+    "bh_align_uneven": (_I, [_P, _P, _I64, _P, _P, _I64, _I, _P, _I64, ctypes.POINTER(AlignOpts),
+                             _P, _P, _P, _P, _P, _P]),
     "bh_align_t": (_I, [_P, _P, _P, _I, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),
     "bh_profile_enable": (_I, [_P, _I]),
     "bh_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),

@@ -159,6 +159,60 @@ class Plan:
                                  _stream()), "bh_expand_ex")
         return out
 
+    def expand_into(self, vols: torch.Tensor, out: torch.Tensor, mode: str = "fp32",
+                    coarse: torch.Tensor | None = None, batch_invariant: bool = False):
+        """Expansion into rows of a wider coefficient array: out [B, ldc, 2]
+        float32 with ldc >= C (the first C entries of each row are written)."""
+        modes = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+        code = modes[mode] | (BH_EXPAND_BATCH_INVARIANT if batch_invariant else 0)
+        B = vols.shape[0]
+        _dev(vols, torch.float32, (B, self.N, self.N, self.N), "vols")
+        ldc = out.shape[1]
+        _dev(out, torch.float32, (B, ldc, 2), "out")
+        if coarse is not None:
+            _dev(coarse, torch.float32, (B, ldc, 2), "coarse")
+        check(lib().bh_expand_into(self._h, _ptr(vols), B, code, _ptr(out), ldc, _ptr(coarse),
+                                   _stream()), "bh_expand_into")
+        return out
+
+    def align_uneven(self, a: torch.Tensor, Lp, templates: torch.Tensor,
+                     tmpl_idx: torch.Tensor | None, bands: Sequence[int], starts: torch.Tensor,
+                     steps: int, step_init: float = 1.0, step_grow: float = 1.25,
+                     step_shrink: float = 0.5, return_all: bool = False,
+                     batch_invariant: bool = False, newton_bands: int = 0, newton_steps: int = 0,
+                     keep: int = 0, min_sep: float = 0.0):
+        """Particles of several bandlimits in one march (see bh_align_uneven):
+        a [B, lda, 2], Lp (B ints, non-increasing), templates [T, ldt, 2]."""
+        import numpy as np
+        B, lda = a.shape[0], a.shape[1]
+        T, ldt = templates.shape[0], templates.shape[1]
+        P = starts.shape[1]
+        _dev(a, torch.float32, (B, lda, 2), "a")
+        _dev(templates, torch.float32, (T, ldt, 2), "templates")
+        _dev(starts, torch.float64, (B, P, 3), "starts")
+        if tmpl_idx is not None:
+            _dev(tmpl_idx, torch.int32, (B,), "tmpl_idx")
+        lp = np.ascontiguousarray(np.asarray(Lp, dtype=np.int32))
+        if lp.shape != (B,):
+            raise ValueError("Lp must hold one bandlimit per particle")
+        bl = (ctypes.c_int32 * len(bands))(*[int(x) for x in bands])
+        o = AlignOpts(ctypes.cast(bl, ctypes.POINTER(ctypes.c_int32)), len(bands), int(steps), P,
+                      float(step_init), float(step_grow), float(step_shrink),
+                      int(bool(batch_invariant)), int(newton_bands), int(newton_steps),
+                      int(keep), float(min_sep))
+        Po = keep if 0 < keep < P else P
+        eu = torch.empty((B, 3), dtype=torch.float64, device=a.device)
+        sc = torch.empty((B,), dtype=torch.float64, device=a.device)
+        ae = torch.empty((B, Po, 3), dtype=torch.float64, device=a.device) if return_all else None
+        asc = torch.empty((B, Po), dtype=torch.float64, device=a.device) if return_all else None
+        check(lib().bh_align_uneven(self._h, _ptr(a), lda, lp.ctypes.data_as(ctypes.c_void_p),
+                                    _ptr(templates), ldt, T, _ptr(tmpl_idx), B, ctypes.byref(o),
+                                    _ptr(starts), _ptr(eu), _ptr(sc), _ptr(ae), _ptr(asc),
+                                    _stream()), "bh_align_uneven")
+        if return_all:
+            return eu, sc, ae, asc
+        return eu, sc
+
     def cross_power(self, a: torch.Tensor, b: torch.Tensor, L: int) -> torch.Tensor:
         """xi [B, E(L), 2] float64 (blocks l, row-major [m][n])."""
         B = a.shape[0]

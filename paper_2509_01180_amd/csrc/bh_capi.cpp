@@ -340,6 +340,29 @@ int bh_expand_ex(bh_plan* p, const float* vols, int64_t B, int mode, float* coef
   });
 }
 
+int bh_expand_into(bh_plan* p, const float* vols, int64_t B, int mode, float* coeffs, int64_t ldc,
+                   float* coarse, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (B < 0 || B > (1LL << 21)) return set_error(BH_EINVAL, "batch size out of range");
+  if (ldc < p->C || ldc > (1LL << 24)) return set_error(BH_EINVAL, "ldc smaller than C(L_max)");
+  const bool invariant = (mode & BH_EXPAND_BATCH_INVARIANT) != 0;
+  mode &= ~BH_EXPAND_BATCH_INVARIANT;
+  if (mode != BH_EXPAND_FP32 && mode != BH_EXPAND_BF16 && mode != BH_EXPAND_BF16X3)
+    return set_error(BH_EINVAL, "unknown expansion mode");
+  if (coarse && mode != BH_EXPAND_BF16X3)
+    return set_error(BH_EINVAL, "a coarse output needs the BF16X3 mode");
+  if (B == 0) return BH_OK;
+  if (!vols || !coeffs) return set_error(BH_EINVAL, "NULL buffer");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    if (mode == BH_EXPAND_FP32)
+      return launch_expand(p, vols, B, coeffs, (hipStream_t)stream, invariant, nullptr, 1, ldc);
+    return launch_expand_bf16(p, vols, B, mode == BH_EXPAND_BF16X3, coeffs, coarse,
+                              (hipStream_t)stream, invariant, ldc);
+  });
+}
+
 int bh_cross_power(bh_plan* p, const float* a, const float* b, int64_t B, int L, double* xi,
                    void* stream) {
   if (!p) return set_error(BH_EINVAL, "plan is NULL");
@@ -465,6 +488,44 @@ int bh_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shi
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
     return launch_align_shifts(p, vols, B, shifts, S, b, *o, starts, euler_out, score_out,
                                shift_out, (hipStream_t)stream);
+  });
+}
+
+int bh_align_uneven(bh_plan* p, const float* a, int64_t lda, const int32_t* Lp,
+                    const float* templates, int64_t ldt, int n_templates, const int32_t* tmpl_idx,
+                    int64_t B, const bh_align_opts* o, const double* starts, double* euler_out,
+                    double* score_out, double* all_euler, double* all_score, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (!o) return set_error(BH_EINVAL, "opts is NULL");
+  if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
+  if (n_templates < 1 || n_templates > (1 << 20)) return set_error(BH_EINVAL, "bad template count");
+  if (n_templates > 1 && !tmpl_idx) return set_error(BH_EINVAL, "template index table is NULL");
+  int rc = check_align_opts(p, o);
+  if (rc != BH_OK) return rc;
+  if (B == 0) return BH_OK;
+  if (!a || !Lp || !templates || !starts || !euler_out || !score_out)
+    return set_error(BH_EINVAL, "NULL buffer");
+  for (int i = 1; i < o->n_bands; ++i)
+    if (o->bands[i] <= o->bands[i - 1]) return set_error(BH_EINVAL, "bands must increase");
+  for (int64_t i = 1; i < B; ++i)
+    if (Lp[i] > Lp[i - 1]) return set_error(BH_EINVAL, "bandlimits must not increase along the batch");
+  if (Lp[B - 1] < o->bands[0]) return set_error(BH_EINVAL, "every particle must take the first band");
+  std::vector<int64_t> active(o->n_bands, 0);
+  int top = 0;                          // largest band any particle takes
+  for (int i = 0; i < o->n_bands; ++i) {
+    int64_t n = 0;
+    while (n < B && Lp[n] >= o->bands[i]) ++n;
+    active[i] = n;
+    if (n > 0) top = o->bands[i];
+  }
+  const int64_t need = p->band_size[top];
+  if (lda < need || ldt < need) return set_error(BH_EINVAL, "row stride below the largest band's C(L)");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    return launch_align(p, a, templates, n_templates > 1 ? tmpl_idx : nullptr, n_templates, B, *o,
+                        starts, euler_out, score_out, all_euler, all_score, (hipStream_t)stream,
+                        lda, ldt, active.data());
   });
 }
 

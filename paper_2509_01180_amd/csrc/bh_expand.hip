@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ part, 
                                                 int64_t M_pad, int64_t C_pad, int64_t B, int64_t C,
                                                 const int32_t* __restrict__ csrc,
                                                 const float* __restrict__ csgn,
-                                                float* __restrict__ coeffs) {
+                                                float* __restrict__ coeffs, int64_t ldc) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= B * C) return;
   const int64_t b = t / C, q = t % C;
@@ -195,14 +195,16 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ part, 
     re += ps[sr];
     if (si >= 0) im += ps[si];
   }
-  coeffs[2 * t] = re * csgn[2 * q];
-  coeffs[2 * t + 1] = (si >= 0) ? im * csgn[2 * q + 1] : 0.0f;
+  const int64_t o = b * ldc + q;
+  coeffs[2 * o] = re * csgn[2 * q];
+  coeffs[2 * o + 1] = (si >= 0) ? im * csgn[2 * q + 1] : 0.0f;
 }
 
 }  // namespace
 
 int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s,
-                  bool batch_invariant, const ShiftTable* shifts, int S) {
+                  bool batch_invariant, const ShiftTable* shifts, int S, int64_t ldc) {
+  if (ldc <= 0) ldc = p->C;
   if (shifts) B *= S;   // one GEMM row per (particle, shift)
   if (B == 0) return BH_OK;
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
@@ -236,7 +238,7 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
   {
   ProfScope ps(p, "reduce", s, B);
   hipLaunchKernelGGL(k_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part, nsplit,
-                     M_pad, p->C_pad, B, p->C, p->csrc, p->csgn, coeffs);
+                     M_pad, p->C_pad, B, p->C, p->csrc, p->csgn, coeffs, ldc);
   }
   BH_HIP(hipGetLastError());
   return BH_OK;

@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_reduce2(const float* __restrict__ part_
                                                  const int32_t* __restrict__ csrc,
                                                  const float* __restrict__ csgn,
                                                  float* __restrict__ coeffs,
-                                                 float* __restrict__ coarse_out) {
+                                                 float* __restrict__ coarse_out, int64_t ldc) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= B * C) return;
   const int64_t b = t / C, q = t % C;
@@ -233,11 +233,12 @@ __global__ __launch_bounds__(256) void k_reduce2(const float* __restrict__ part_
     }
   }
   const float gr = csgn[2 * q], gi = csgn[2 * q + 1];
-  coeffs[2 * t] = (cre + rre) * gr;
-  coeffs[2 * t + 1] = (si >= 0) ? (cim + rim) * gi : 0.0f;
+  const int64_t oc = b * ldc + q;
+  coeffs[2 * oc] = (cre + rre) * gr;
+  coeffs[2 * oc + 1] = (si >= 0) ? (cim + rim) * gi : 0.0f;
   if (coarse_out) {
-    coarse_out[2 * t] = cre * gr;
-    coarse_out[2 * t + 1] = (si >= 0) ? cim * gi : 0.0f;
+    coarse_out[2 * oc] = cre * gr;
+    coarse_out[2 * oc + 1] = (si >= 0) ? cim * gi : 0.0f;
   }
 }
 
@@ -262,7 +263,8 @@ int ensure_bf16_basis(bh_plan* p) {
 }
 
 int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, float* coeffs,
-                       float* coarse_out, hipStream_t s, bool batch_invariant) {
+                       float* coarse_out, hipStream_t s, bool batch_invariant, int64_t ldc) {
+  if (ldc <= 0) ldc = p->C;
   if (B == 0) return BH_OK;
   int rc = ensure_bf16_basis(p);
   if (rc != BH_OK) return rc;
@@ -303,7 +305,7 @@ int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, fl
     const int64_t tot = B * p->C;
     hipLaunchKernelGGL(k_reduce2, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part_c,
                        part_r, nsplit, M_pad, p->C_pad, B, p->C, p->csrc, p->csgn, coeffs,
-                       coarse_out);
+                       coarse_out, ldc);
   }
   BH_HIP(hipGetLastError());
   return BH_OK;

@@ -134,10 +134,13 @@ struct ShiftTable {
 };
 // With `shifts` the rows are the B*S shifted volumes (particle-major) of
 // the S integer voxel shifts.
+// ldc: complex stride between particles' coefficient rows (0: C(L_max)).
 int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s,
-                  bool batch_invariant = false, const ShiftTable* shifts = nullptr, int S = 1);
+                  bool batch_invariant = false, const ShiftTable* shifts = nullptr, int S = 1,
+                  int64_t ldc = 0);
 int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, float* coeffs,
-                       float* coarse_out, hipStream_t s, bool batch_invariant = false);
+                       float* coarse_out, hipStream_t s, bool batch_invariant = false,
+                       int64_t ldc = 0);
 int launch_cross_power_dense(bh_plan* p, const DevBand& band, const float* a, const float* b,
                              int64_t B, double* xi, hipStream_t s);
 int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const float* b, int64_t B,
@@ -149,9 +152,12 @@ int launch_degree_energy(bh_plan* p, const DevBand& band, const float* a, const 
 int launch_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shifts_host,
                         int S, const float* b, const bh_align_opts& o, const double* starts,
                         double* euler_out, double* score_out, int32_t* shift_out, hipStream_t s);
+// lda / ldt: complex strides of the particle and template rows (0: C(L_max));
+// active: particles taking each band (a prefix of the batch; NULL: all B).
 int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl, int n_tmpl,
                  int64_t B, const bh_align_opts& o,
                  const double* starts, double* euler_out, double* score_out, double* all_euler,
-                 double* all_score, hipStream_t s);
+                 double* all_score, hipStream_t s, int64_t lda = 0, int64_t ldt = 0,
+                 const int64_t* active = nullptr);
 
 }  // namespace bh

@@ -95,7 +95,8 @@ __device__ inline int64_t template_of(const int32_t* __restrict__ tmpl, int n_tm
 }
 
 // Class-major weighted cross-power of one band: X[pb][e] = {X1re, X1im, X2re, X2im}.
-__global__ void k_xi_classes(const float* __restrict__ a, const float* __restrict__ btab, int64_t C,
+__global__ void k_xi_classes(const float* __restrict__ a, int64_t lda,
+                             const float* __restrict__ btab, int64_t ldt,
                              const int32_t* __restrict__ tmpl, int n_tmpl,
                              int64_t n_entries, const int32_t* __restrict__ sel,
                              const double* __restrict__ wt, const int32_t* __restrict__ deg_start,
@@ -105,8 +106,8 @@ __global__ void k_xi_classes(const float* __restrict__ a, const float* __restric
   if (e >= n_entries) return;
   const int l = sel[4 * e], m = sel[4 * e + 1], n = sel[4 * e + 2];
   const double w1 = wt[2 * e], w2 = wt[2 * e + 1];
-  const float* ap = a + pb * 2 * C;
-  const float* b = btab + template_of(tmpl, n_tmpl, pb) * 2 * C;
+  const float* ap = a + pb * 2 * lda;
+  const float* b = btab + template_of(tmpl, n_tmpl, pb) * 2 * ldt;
   double x1r = 0, x1i = 0, x2r = 0, x2i = 0;
   for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
     const int o = deg_off[i];
@@ -127,14 +128,15 @@ __global__ void k_xi_classes(const float* __restrict__ a, const float* __restric
 }
 
 // W_b = sum_l l(l+1) ||a_l|| ||b_l|| over the band; one block per particle.
-__global__ void k_band_weight(const float* __restrict__ a, const float* __restrict__ btab, int64_t C,
+__global__ void k_band_weight(const float* __restrict__ a, int64_t lda,
+                              const float* __restrict__ btab, int64_t ldt,
                               const int32_t* __restrict__ tmpl, int n_tmpl,
                               int L, const int32_t* __restrict__ deg_start,
                               const int32_t* __restrict__ deg_off, double* __restrict__ Wb) {
   __shared__ double part[BH_MAX_L + 1];
   const int64_t pb = blockIdx.x;
-  const float* ap = a + pb * 2 * C;
-  const float* b = btab + template_of(tmpl, n_tmpl, pb) * 2 * C;
+  const float* ap = a + pb * 2 * lda;
+  const float* b = btab + template_of(tmpl, n_tmpl, pb) * 2 * ldt;
   for (int l = threadIdx.x; l <= L; l += blockDim.x) {
     double na = 0.0, nb = 0.0;
     for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
@@ -687,14 +689,17 @@ void launch_march_any(int W, int G, bh_plan* p, int64_t B, hipStream_t s, const 
 }
 
 int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b,
-                 const int32_t* tmpl, int n_tmpl, int64_t B, double** X, hipStream_t s) {
+                 const int32_t* tmpl, int n_tmpl, int64_t B, double** X, hipStream_t s,
+                 int64_t lda = 0, int64_t ldt = 0) {
+  if (lda <= 0) lda = p->C;
+  if (ldt <= 0) ldt = p->C;
   // + kTablePad entries: the score loop reads up to three entries ahead
   int rc = grow(p->xi_scr, ((size_t)B * band.n_entries + kTablePad) * 4 * sizeof(double));
   if (rc != BH_OK) return rc;
   *X = (double*)p->xi_scr.ptr;
   ProfScope ps(p, "xi_classes", s, B);
   hipLaunchKernelGGL(k_xi_classes, dim3((unsigned)((band.n_entries + 127) / 128), (unsigned)B),
-                     dim3(128), 0, s, a, b, p->C, tmpl, n_tmpl, band.n_entries, band.sel, band.wt,
+                     dim3(128), 0, s, a, lda, b, ldt, tmpl, n_tmpl, band.n_entries, band.sel, band.wt,
                      band.deg_start, band.deg_off, *X);
   BH_HIP(hipGetLastError());
   return BH_OK;
@@ -742,7 +747,10 @@ int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const floa
 
 int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl, int n_tmpl,
                  int64_t B, const bh_align_opts& o, const double* starts, double* euler_out,
-                 double* score_out, double* all_euler, double* all_score, hipStream_t s) {
+                 double* score_out, double* all_euler, double* all_score, hipStream_t s,
+                 int64_t lda, int64_t ldt, const int64_t* active) {
+  if (lda <= 0) lda = p->C;
+  if (ldt <= 0) ldt = p->C;
   int P = o.n_restarts;
   const bool prune = o.n_keep > 0 && o.n_keep < P;
   const int K = prune ? o.n_keep : P;
@@ -762,13 +770,16 @@ int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl
     if ((rc = get_band(p, o.bands[i], &band)) != BH_OK) return rc;
     bands.push_back(band);
   }
+  const int64_t B_all = B;
   for (int bi = 0; bi < o.n_bands; ++bi) {
     const DevBand* band = bands[bi];
+    B = active ? active[bi] : B_all;     // the particles that take this band
+    if (B == 0) continue;
     double* X = nullptr;
-    if ((rc = prepare_band(p, *band, a, b, tmpl, n_tmpl, B, &X, s)) != BH_OK) return rc;
+    if ((rc = prepare_band(p, *band, a, b, tmpl, n_tmpl, B, &X, s, lda, ldt)) != BH_OK) return rc;
     {
       ProfScope ps(p, "band_weight", s, B);
-      hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, b, p->C, tmpl,
+      hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, lda, b, ldt, tmpl,
                          n_tmpl, band->L, band->deg_start, band->deg_off, Wb);
     }
     BH_HIP(hipGetLastError());
@@ -801,6 +812,7 @@ int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl
       P = K;
     }
   }
+  B = B_all;
   {
     ProfScope ps(p, "select", s, B);
     hipLaunchKernelGGL(k_select, dim3((unsigned)B), dim3(64), 0, s, state, sscore, P, euler_out,
