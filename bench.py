@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--calib-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed "
                          "region (reference kernel for hardware traffic counters)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the launch-shape candidates for this workload first and use the fastest")
     ap.add_argument("--method", choices=("march", "paper"), default="march",
                     help="march: the gradient march over bands 8-16-24-32 with 64 restarts; "
                          "paper: bands chosen by the energy ratio, candidates from the lowest "
@@ -197,6 +199,12 @@ def main():
     print(f"# plan built in {t_plan:.2f} s", file=sys.stderr, flush=True)
 
     a_coarse = torch.empty_like(a) if args.precision == "bf16x3" else None
+    tuned = None
+    if args.autotune:
+        t_tune = time.perf_counter()
+        tuned = plan.autotune(B, w.bands, restarts=w.restarts)
+        tuned["seconds"] = round(time.perf_counter() - t_tune, 2)
+        print(f"# autotuned {tuned}", file=sys.stderr, flush=True)
 
     def step():
         if args.precision == "plain":
@@ -304,6 +312,8 @@ def main():
                      "p90_deg_vs_planted": round(float(np.percentile(ang, 90)), 3)},
         "setup": {"input_generation_s": round(t_gen, 1), "plan_build_s": round(t_plan, 2)},
     }
+    if tuned is not None:
+        result["autotuned"] = tuned
 
     if args.precision == "bf16x3":
         # the plain path on the same inputs (untimed), for the comparison

@@ -293,6 +293,28 @@ int bh_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shi
                     double* euler_out, double* score_out, int32_t* shift_out, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Autotuning: launch shapes chosen by timing on this GPU.
+ * bh_plan_autotune times, on random data of B particles (synchronously, on
+ * `stream`), the candidate shapes and keeps the fastest in the plan:
+ *  BH_TUNE_MARCH:       waves per workgroup of the ascent kernel
+ *                       (4, 5, 6, 8, 10, 12, 16) for each band of `bands`,
+ *                       n_restarts restarts, 2 ascent steps per trial;
+ *  BH_TUNE_EXPAND:      split-K factor (1..16) of the FP32 expansion GEMM for
+ *                       B particles' tile count;
+ *  BH_TUNE_EXPAND_BF16: the same for the split-BF16 GEMM.
+ * Later calls use the tuned choices (the tuned wave count depends on the
+ * band only, so batch-invariant calls use it too; batch-invariant expansions
+ * keep their fixed split).  bh_plan_tuning reports, for band L and batch
+ * size B, the tuned wave count (0: built-in rule) and the split-K factors
+ * the expansions would use.
+ * ------------------------------------------------------------------- */
+enum { BH_TUNE_MARCH = 1, BH_TUNE_EXPAND = 2, BH_TUNE_EXPAND_BF16 = 4 };
+int bh_plan_autotune(bh_plan* p, int64_t B, int n_restarts, const int32_t* bands, int n_bands,
+                     int what, void* stream);
+int bh_plan_tuning(const bh_plan* p, int L, int64_t B, int* waves, int* split_f32,
+                   int* split_bf16);
+
+/* ---------------------------------------------------------------------
  * Per-kernel timing (for measurement; off by default).
  * bh_profile_enable(p, 1) synchronises the device, clears earlier records
  * and starts recording a pair of HIP events on the call's stream around

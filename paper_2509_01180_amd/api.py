@@ -111,6 +111,36 @@ class Plan:
     def num_coeffs(self, L: int) -> int:
         return check(lib().bh_plan_num_coeffs(self._h, int(L)), "bh_plan_num_coeffs")
 
+    # ------------------------------------------------------- autotuning --
+    def autotune(self, B: int, bands: Sequence[int] = (), restarts: int = 64,
+                 what: Sequence[str] = ("march", "expand", "expand_bf16")) -> dict:
+        """Time the candidate launch shapes on this GPU for batch size B and
+        keep the fastest in the plan (see bh_plan_autotune); returns the
+        choices now in effect for each band and for B."""
+        from ._lib import BH_TUNE_EXPAND, BH_TUNE_EXPAND_BF16, BH_TUNE_MARCH
+        flags = {"march": BH_TUNE_MARCH, "expand": BH_TUNE_EXPAND,
+                 "expand_bf16": BH_TUNE_EXPAND_BF16}
+        code = 0
+        for w in what:
+            code |= flags[w]
+        bl = (ctypes.c_int32 * max(1, len(bands)))(*[int(x) for x in bands])
+        check(lib().bh_plan_autotune(self._h, int(B), int(restarts), bl, len(bands), code,
+                                     _stream()), "bh_plan_autotune")
+        return self.tuning(B, bands)
+
+    def tuning(self, B: int, bands: Sequence[int] = ()) -> dict:
+        """{"waves": {L: tuned wave count or 0}, "split_f32": s, "split_bf16": s}."""
+        w, s32, s16 = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        out = {"waves": {}}
+        for L in bands:
+            check(lib().bh_plan_tuning(self._h, int(L), int(B), ctypes.byref(w), ctypes.byref(s32),
+                                       ctypes.byref(s16)), "bh_plan_tuning")
+            out["waves"][int(L)] = w.value
+        check(lib().bh_plan_tuning(self._h, 0, int(B), ctypes.byref(w), ctypes.byref(s32),
+                                   ctypes.byref(s16)), "bh_plan_tuning")
+        out["split_f32"], out["split_bf16"] = s32.value, s16.value
+        return out
+
     # ------------------------------------------------------- profiling --
     def profile(self, enable: bool = True) -> None:
         """Start (clearing earlier records) or stop per-kernel event timing."""

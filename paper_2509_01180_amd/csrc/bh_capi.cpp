@@ -260,6 +260,43 @@ void bh_plan_destroy(bh_plan* p) {
   delete p;
 }
 
+int bh_plan_autotune(bh_plan* p, int64_t B, int n_restarts, const int32_t* bands, int n_bands,
+                     int what, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (B < 1 || B > (1LL << 16)) return set_error(BH_EINVAL, "tuning batch outside 1..65536");
+  if (n_restarts < 1 || n_restarts > 1024) return set_error(BH_EINVAL, "bad restart count");
+  if ((what & BH_TUNE_MARCH) && (n_bands < 1 || n_bands > 64 || !bands))
+    return set_error(BH_EINVAL, "bad band list");
+  if (what & BH_TUNE_MARCH)
+    for (int i = 0; i < n_bands; ++i)
+      if (bands[i] < 0 || bands[i] > p->L_max) return set_error(BH_EINVAL, "band outside 0..L_max");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    const hipStream_t s = (hipStream_t)stream;
+    int rc = BH_OK;
+    if ((what & BH_TUNE_MARCH) && (rc = tune_march(p, B, n_restarts, bands, n_bands, s)) != BH_OK)
+      return rc;
+    if ((what & BH_TUNE_EXPAND) && (rc = tune_expand_f32(p, B, s)) != BH_OK) return rc;
+    if ((what & BH_TUNE_EXPAND_BF16) && (rc = tune_expand_bf16(p, B, s)) != BH_OK) return rc;
+    BH_HIP(hipStreamSynchronize(s));
+    return BH_OK;
+  });
+}
+
+int bh_plan_tuning(const bh_plan* p, int L, int64_t B, int* waves, int* split_f32,
+                   int* split_bf16) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (L < 0 || L > p->L_max) return set_error(BH_EINVAL, "L outside 0..L_max");
+  if (B < 1) return set_error(BH_EINVAL, "batch size out of range");
+  if (waves) *waves = p->tuned_waves[L];
+  const int64_t mt = (B + kGemmBM - 1) / kGemmBM;
+  const int64_t nt = p->C_pad / kGemmBN, nk = p->V_pad / kGemmBK;
+  if (split_f32) *split_f32 = expand_split(mt, nt, nk, false, &p->tuned_split[0]);
+  if (split_bf16) *split_bf16 = expand_split(mt, nt, nk, false, &p->tuned_split[1]);
+  return BH_OK;
+}
+
 int bh_profile_enable(bh_plan* p, int enable) {
   if (!p) return set_error(BH_EINVAL, "plan is NULL");
   return guarded([&]() -> int {

@@ -10,6 +10,8 @@
 //               layout (re, im) for m = -l..l.
 #include "bh_internal.h"
 
+#include <algorithm>
+
 namespace bh {
 namespace {
 
@@ -210,7 +212,7 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
   const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
   const int64_t nk_total = p->V_pad / BK;           // multiple of 16
-  const int nsplit = expand_split(mt, nt, nk_total, batch_invariant);
+  const int nsplit = expand_split(mt, nt, nk_total, batch_invariant, &p->tuned_split[0]);
   const int nk = (int)(nk_total / nsplit);
   int rc;
   if ((rc = grow(p->gathered, (size_t)p->V_pad * M_pad * sizeof(float))) != BH_OK) return rc;
@@ -241,6 +243,48 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
                      M_pad, p->C_pad, B, p->C, p->csrc, p->csgn, coeffs, ldc);
   }
   BH_HIP(hipGetLastError());
+  return BH_OK;
+}
+
+int tune_expand_f32(bh_plan* p, int64_t B, hipStream_t s) {
+  const int64_t M_pad = ((B + BM - 1) / BM) * BM;
+  const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
+  const int64_t nk_total = p->V_pad / BK;
+  int rc;
+  if ((rc = grow(p->gathered, (size_t)p->V_pad * M_pad * sizeof(float))) != BH_OK) return rc;
+  if ((rc = grow(p->partial, (size_t)16 * M_pad * p->C_pad * sizeof(float))) != BH_OK) return rc;
+  float* Ft = (float*)p->gathered.ptr;
+  float* part = (float*)p->partial.ptr;
+  // timing data: the basis itself stands in for the volumes (any finite values)
+  BH_HIP(hipMemcpyAsync(Ft, p->psi, (size_t)p->V_pad * std::min(M_pad, p->C_pad) * sizeof(float),
+                        hipMemcpyDeviceToDevice, s));
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  float best_ms = 1e30f;
+  int best = 1;
+  for (int ns = 1; ns <= 16; ns *= 2) {
+    if (nk_total / ns < 8) break;
+    float ms = 0.0f;
+    for (int rep = 0; rep < 3; ++rep) {
+      hipEventRecord(e0, s);
+      hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)(mt * nt * ns)), dim3(256), 0, s, Ft, p->psi,
+                         part, M_pad, p->C_pad, (int)(nk_total / ns), ns);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float t = 0.0f;
+      hipEventElapsedTime(&t, e0, e1);
+      if (rep > 0) ms += t;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = ns;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  BH_HIP(hipGetLastError());
+  p->tuned_split[0][mt] = best;
   return BH_OK;
 }
 

@@ -21,6 +21,8 @@
 // takes it in.
 #include "bh_internal.h"
 
+#include <algorithm>
+
 namespace bh {
 namespace {
 
@@ -271,7 +273,7 @@ int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, fl
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
   const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
   const int64_t nk_total = p->V_pad / BK;   // multiple of 16
-  const int nsplit = expand_split(mt, nt, nk_total, batch_invariant);
+  const int nsplit = expand_split(mt, nt, nk_total, batch_invariant, &p->tuned_split[1]);
   const int nk = (int)(nk_total / nsplit);
   const size_t fbytes = (size_t)M_pad * p->V_pad * sizeof(uint16_t);
   const size_t pbytes = (size_t)nsplit * M_pad * p->C_pad * sizeof(float);
@@ -308,6 +310,54 @@ int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, fl
                        coarse_out, ldc);
   }
   BH_HIP(hipGetLastError());
+  return BH_OK;
+}
+
+int tune_expand_bf16(bh_plan* p, int64_t B, hipStream_t s) {
+  int rc = ensure_bf16_basis(p);
+  if (rc != BH_OK) return rc;
+  const int64_t M_pad = ((B + BM - 1) / BM) * BM;
+  const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
+  const int64_t nk_total = p->V_pad / BK;
+  const size_t fbytes = (size_t)M_pad * p->V_pad * sizeof(uint16_t);
+  if ((rc = grow(p->gathered, 2 * fbytes)) != BH_OK) return rc;
+  if ((rc = grow(p->partial, (size_t)2 * 16 * M_pad * p->C_pad * sizeof(float))) != BH_OK)
+    return rc;
+  uint16_t* fh = (uint16_t*)p->gathered.ptr;
+  uint16_t* fl = fh + (size_t)M_pad * p->V_pad;
+  float* part = (float*)p->partial.ptr;
+  // timing data: BF16 basis values stand in for the volumes (any finite values)
+  const size_t n = (size_t)std::min(M_pad, p->C_pad) * p->V_pad * sizeof(uint16_t);
+  BH_HIP(hipMemcpyAsync(fh, p->psi_h, n, hipMemcpyDeviceToDevice, s));
+  BH_HIP(hipMemcpyAsync(fl, p->psi_l, n, hipMemcpyDeviceToDevice, s));
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  float best_ms = 1e30f;
+  int best = 1;
+  for (int ns = 1; ns <= 16; ns *= 2) {
+    if (nk_total / ns < 8) break;
+    float ms = 0.0f;
+    for (int rep = 0; rep < 3; ++rep) {
+      hipEventRecord(e0, s);
+      hipLaunchKernelGGL((k_gemm_bf16<true, true>), dim3((unsigned)(mt * nt * ns)), dim3(256), 0, s,
+                         fh, fl, p->psi_h, p->psi_l, part, part + (size_t)ns * M_pad * p->C_pad,
+                         M_pad, p->C_pad, p->V_pad, (int)(nk_total / ns), ns);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float t = 0.0f;
+      hipEventElapsedTime(&t, e0, e1);
+      if (rep > 0) ms += t;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = ns;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  BH_HIP(hipGetLastError());
+  p->tuned_split[1][mt] = best;
   return BH_OK;
 }
 

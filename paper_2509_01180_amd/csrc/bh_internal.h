@@ -93,6 +93,9 @@ struct bh_plan {
   bh::Buffer gathered, partial, xi_scr, state_scr, misc_scr, prune_scr, shift_scr;
   std::map<int, bh::DevBand> bands;
   bh::Profiler prof;
+  // autotuned launch shapes (0 / absent: the built-in rules)
+  int tuned_waves[BH_MAX_L + 1] = {};
+  std::map<int64_t, int> tuned_split[2];   // particle tiles -> split-K (FP32, BF16 GEMM)
 };
 
 namespace bh {
@@ -121,8 +124,13 @@ int build_basis(bh_plan* p);
 // than 1024 tiles and each split keeps at least 8 K-steps.  With
 // batch_invariant the particle-tile count is taken as 8 (1024 particles)
 // whatever the batch, so a particle's sums never depend on the batch size.
-inline int expand_split(int64_t mt, int64_t nt, int64_t nk_total, bool batch_invariant) {
+inline int expand_split(int64_t mt, int64_t nt, int64_t nk_total, bool batch_invariant,
+                        const std::map<int64_t, int>* tuned = nullptr) {
   if (batch_invariant) mt = 8;
+  if (tuned && !batch_invariant) {
+    const auto it = tuned->find(mt);
+    if (it != tuned->end()) return it->second;
+  }
   int nsplit = 1;
   while (nsplit < 16 && mt * nt * nsplit < 1024 && (nk_total / (nsplit * 2)) >= 8) nsplit *= 2;
   return nsplit;
@@ -149,6 +157,11 @@ int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const floa
 int launch_degree_energy(bh_plan* p, const DevBand& band, const float* a, const float* b,
                          const int32_t* tmpl, int n_tmpl, int64_t B, double* energy,
                          hipStream_t s);
+// Autotuning (see bh_plan_autotune): time the candidate shapes on random
+// data of B particles and record the fastest in the plan.
+int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, hipStream_t s);
+int tune_expand_f32(bh_plan* p, int64_t B, hipStream_t s);
+int tune_expand_bf16(bh_plan* p, int64_t B, hipStream_t s);
 int launch_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shifts_host,
                         int S, const float* b, const bh_align_opts& o, const double* starts,
                         double* euler_out, double* score_out, int32_t* shift_out, hipStream_t s);

@@ -600,8 +600,9 @@ __global__ void k_select_shift(const double* __restrict__ eu, const double* __re
   shift_out[b] = best;
 }
 
-int pick_waves(int64_t groups, int L, bool batch_invariant = false) {
+int pick_waves(const bh_plan* p, int64_t groups, int L, bool batch_invariant = false) {
   if (BH_SCORE_FIXED_W > 0) return BH_SCORE_FIXED_W;
+  if (p->tuned_waves[L] > 0) return p->tuned_waves[L];
   // Measured on MI355X (1000 particles x 64 restarts, bands 8..32): 12 waves
   // per workgroup at 6 waves per SIMD (two workgroups per CU) is fastest for
   // L > 8, 4 waves for L <= 8; small batches spread one particle over 16
@@ -736,7 +737,7 @@ int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const floa
   if (rc != BH_OK) return rc;
   const int64_t chunks = (R + 63) / 64;
   const dim3 grid((unsigned)chunks, (unsigned)B);
-  const int W = pick_waves(chunks * B, band.L);
+  const int W = pick_waves(p, chunks * B, band.L);
   if (hess)
     launch_correlate_any<true>(W, p, grid, s, band, X, euler, R, score, grad, hess);
   else
@@ -786,7 +787,7 @@ int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl
     // lanes per particle: 64, or fewer when the (pruned) restarts fit
     const int G = P <= 8 ? 8 : (P <= 16 ? 16 : (P <= 32 ? 32 : 64));
     const int64_t groups = (G == 64) ? (P + 63) / 64 * B : (B + 64 / G - 1) / (64 / G);
-    const int W = pick_waves(groups, band->L, o.batch_invariant != 0);
+    const int W = pick_waves(p, groups, band->L, o.batch_invariant != 0);
     const bool newton = bi >= o.n_bands - o.newton_bands;
     if (newton) {
       const int steps = o.newton_steps > 0 ? o.newton_steps : o.steps_per_band;
@@ -826,6 +827,97 @@ int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl
     BH_HIP(hipMemcpyAsync(all_score, sscore, (size_t)B * P * sizeof(double),
                           hipMemcpyDeviceToDevice, s));
   return BH_OK;
+}
+
+namespace {
+// x[i] = uniform in [-1, 1) from a counter hash of (i, seed) (timing data only).
+__global__ void k_fill_random(float* __restrict__ x, int64_t n, uint32_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + seed;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  x[i] = (float)((double)(z >> 11) * (1.0 / 4503599627370496.0) - 1.0);
+}
+
+__global__ void k_widen(const float* __restrict__ x, int64_t n, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = 3.14159265358979 * (double)x[i];
+}
+}  // namespace
+
+int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, hipStream_t s) {
+  const int64_t na = B * p->C * 2, nb = p->C * 2, ns = B * P * 3;
+  float* buf = nullptr;
+  double* starts = nullptr;
+  if (hipMalloc((void**)&buf, (size_t)(na + nb + ns) * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&starts, (size_t)ns * sizeof(double)) != hipSuccess) {
+    hipFree(buf);
+    return set_error(BH_ENOMEM, "autotune buffers");
+  }
+  float* a = buf;
+  float* b = buf + na;
+  hipLaunchKernelGGL(k_fill_random, dim3((unsigned)((na + nb + ns + 255) / 256)), dim3(256), 0, s,
+                     buf, na + nb + ns, 12345u);
+  hipLaunchKernelGGL(k_widen, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, buf + na + nb,
+                     ns, starts);
+  int rc = BH_OK;
+  if ((rc = grow(p->state_scr, (size_t)B * P * 4 * sizeof(double))) != BH_OK ||
+      (rc = grow(p->misc_scr, (size_t)B * sizeof(double))) != BH_OK) {
+    hipFree(buf);
+    hipFree(starts);
+    return rc;
+  }
+  double* state = (double*)p->state_scr.ptr;
+  double* sscore = state + (size_t)B * P * 3;
+  double* Wb = (double*)p->misc_scr.ptr;
+  bh_align_opts o = {};
+  o.step_init = 1.0;
+  o.step_grow = 1.25;
+  o.step_shrink = 0.5;
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  for (int bi = 0; bi < n_bands && rc == BH_OK; ++bi) {
+    const DevBand* band = nullptr;
+    if ((rc = get_band(p, bands[bi], &band)) != BH_OK) break;
+    double* X = nullptr;
+    if ((rc = prepare_band(p, *band, a, b, nullptr, 1, B, &X, s)) != BH_OK) break;
+    hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, p->C, b, p->C,
+                       nullptr, 1, band->L, band->deg_start, band->deg_off, Wb);
+    float best_ms = 1e30f;
+    int best_w = 0;
+    for (int W : {4, 5, 6, 8, 10, 12, 16}) {
+      if (W > 2 * band->L + 1 && W > 4) continue;
+      float ms = 0.0f;
+      for (int rep = 0; rep < 3; ++rep) {   // the first run warms up
+        hipMemcpyAsync(state, starts, (size_t)ns * sizeof(double), hipMemcpyDeviceToDevice, s);
+        hipEventRecord(e0, s);
+        launch_march_any<false>(W, 64, p, B, s, *band, X, Wb, P, 2, o, state, sscore);
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float t = 0.0f;
+        hipEventElapsedTime(&t, e0, e1);
+        if (rep > 0) ms += t;
+      }
+      if (hipGetLastError() != hipSuccess) {
+        rc = set_error(BH_EDEVICE, "autotune launch failed");
+        break;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_w = W;
+      }
+    }
+    if (rc == BH_OK) p->tuned_waves[band->L] = best_w;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipStreamSynchronize(s);
+  hipFree(buf);
+  hipFree(starts);
+  return rc;
 }
 
 int launch_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shifts_host,

@@ -1,0 +1,43 @@
+"""Autotuning (bh_plan_autotune): the tuned shapes are valid candidates, the
+plan reports them, and alignment and expansion after tuning agree with the
+results before it (a different wave split only reorders sums)."""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import cuda_device, normwise, say, to_complex
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_choices_and_results():
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    dev = cuda_device()
+    N, L, B, P = 32, 16, 256, 64
+    rng = np.random.default_rng(8)
+    bl = synth.blob_template(rng, 20)
+    vols = np.stack([synth.add_noise(synth.render_blobs(bl, N, g), 0.5, rng) for g in
+                     synth.quat_to_matrix(synth.haar_quaternions(rng, B))]).astype(np.float32)
+    starts = torch.from_numpy(synth.matrix_to_euler_zyz(synth.quat_to_matrix(
+        synth.haar_quaternions(rng, B * P))).reshape(B, P, 3)).to(dev)
+    say(f"autotune N={N} L={L} B={B}")
+    plan = Plan(N, L, device=0)
+    b = plan.expand(torch.from_numpy(synth.render_blobs(bl, N)[None].astype(np.float32)).to(dev))[0]
+    v = torch.from_numpy(vols).to(dev)
+    a0 = plan.expand(v)
+    e0, s0 = plan.align(a0, b.contiguous(), (8, 16), starts, 10)
+    before = plan.tuning(B, (8, 16))
+    assert before["waves"] == {8: 0, 16: 0}
+    got = plan.autotune(B, (8, 16), restarts=P)
+    print("tuned", got)
+    assert all(w in (4, 5, 6, 8, 10, 12, 16) for w in got["waves"].values())
+    assert got["split_f32"] in (1, 2, 4, 8, 16) and got["split_bf16"] in (1, 2, 4, 8, 16)
+    a1 = plan.expand(v)
+    e1, s1 = plan.align(a1, b.contiguous(), (8, 16), starts, 10)
+    torch.cuda.synchronize()
+    assert np.all(normwise(to_complex(a1), to_complex(a0)) <= 1e-6)
+    s0, s1 = s0.cpu().numpy(), s1.cpu().numpy()
+    assert np.max(np.abs(s1 - s0) / np.abs(s0)) <= 1e-6
+    plan.close()
