@@ -298,21 +298,27 @@ int bh_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shi
  * `stream`), the candidate shapes and keeps the fastest in the plan:
  *  BH_TUNE_MARCH:       waves per workgroup of the ascent kernel
  *                       (4, 5, 6, 8, 10, 12, 16) for each band of `bands`,
- *                       n_restarts restarts, 2 ascent steps per trial;
+ *                       n_restarts restarts, 2 ascent steps per trial, then
+ *                       whether persistent workgroups (only as many as are
+ *                       resident, looping over the particles) are faster;
  *  BH_TUNE_EXPAND:      split-K factor (1..16) of the FP32 expansion GEMM for
  *                       B particles' tile count;
  *  BH_TUNE_EXPAND_BF16: the same for the split-BF16 GEMM.
  * Later calls use the tuned choices (the tuned wave count depends on the
  * band only, so batch-invariant calls use it too; batch-invariant expansions
  * keep their fixed split).  bh_plan_tuning reports, for band L and batch
- * size B, the tuned wave count (0: built-in rule) and the split-K factors
- * the expansions would use.
+ * size B, the tuned wave count (0: built-in rule), whether its launches are
+ * persistent, and the split-K factors the expansions would use.
  * ------------------------------------------------------------------- */
 enum { BH_TUNE_MARCH = 1, BH_TUNE_EXPAND = 2, BH_TUNE_EXPAND_BF16 = 4 };
 int bh_plan_autotune(bh_plan* p, int64_t B, int n_restarts, const int32_t* bands, int n_bands,
                      int what, void* stream);
-int bh_plan_tuning(const bh_plan* p, int L, int64_t B, int* waves, int* split_f32,
-                   int* split_bf16);
+int bh_plan_tuning(const bh_plan* p, int L, int64_t B, int* waves, int* persistent,
+                   int* split_f32, int* split_bf16);
+/* Pin the ascent kernel's shape for band L (e.g. from a saved tuning run):
+ * waves 0 (built-in rule) or one of 4, 5, 6, 8, 10, 12, 16 (at most 2L+1
+ * unless 4); persistent 0/1. */
+int bh_plan_set_tuning(bh_plan* p, int L, int waves, int persistent);
 
 /* ---------------------------------------------------------------------
  * Per-kernel timing (for measurement; off by default).

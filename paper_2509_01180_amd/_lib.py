@@ -75,7 +75,9 @@ SIGNATURES = {
                              _P, _P, _P, _P, _P, _P]),
     "bh_align_t": (_I, [_P, _P, _P, _I, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),
     "bh_plan_autotune": (_I, [_P, _I64, _I, _P, _I, _I, _P]),
-    "bh_plan_tuning": (_I, [_P, _I, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "bh_plan_tuning": (_I, [_P, _I, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
+                            ctypes.POINTER(_I)]),
+    "bh_plan_set_tuning": (_I, [_P, _I, _I, _I]),
     "bh_profile_enable": (_I, [_P, _I]),
     "bh_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(_I64)]),

@@ -128,16 +128,23 @@ class Plan:
                                      _stream()), "bh_plan_autotune")
         return self.tuning(B, bands)
 
+    def set_tuning(self, L: int, waves: int = 0, persistent: bool = False) -> None:
+        """Pin the ascent kernel's wave count / persistence for band L."""
+        check(lib().bh_plan_set_tuning(self._h, int(L), int(waves), int(bool(persistent))),
+              "bh_plan_set_tuning")
+
     def tuning(self, B: int, bands: Sequence[int] = ()) -> dict:
-        """{"waves": {L: tuned wave count or 0}, "split_f32": s, "split_bf16": s}."""
-        w, s32, s16 = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        out = {"waves": {}}
+        """{"waves": {L: tuned wave count or 0}, "persistent": {L: 0/1},
+        "split_f32": s, "split_bf16": s}."""
+        w, ps, s32, s16 = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        out = {"waves": {}, "persistent": {}}
         for L in bands:
-            check(lib().bh_plan_tuning(self._h, int(L), int(B), ctypes.byref(w), ctypes.byref(s32),
-                                       ctypes.byref(s16)), "bh_plan_tuning")
+            check(lib().bh_plan_tuning(self._h, int(L), int(B), ctypes.byref(w), ctypes.byref(ps),
+                                       ctypes.byref(s32), ctypes.byref(s16)), "bh_plan_tuning")
             out["waves"][int(L)] = w.value
-        check(lib().bh_plan_tuning(self._h, 0, int(B), ctypes.byref(w), ctypes.byref(s32),
-                                   ctypes.byref(s16)), "bh_plan_tuning")
+            out["persistent"][int(L)] = ps.value
+        check(lib().bh_plan_tuning(self._h, 0, int(B), ctypes.byref(w), ctypes.byref(ps),
+                                   ctypes.byref(s32), ctypes.byref(s16)), "bh_plan_tuning")
         out["split_f32"], out["split_bf16"] = s32.value, s16.value
         return out
 

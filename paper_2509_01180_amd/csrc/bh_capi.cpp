@@ -284,12 +284,25 @@ int bh_plan_autotune(bh_plan* p, int64_t B, int n_restarts, const int32_t* bands
   });
 }
 
-int bh_plan_tuning(const bh_plan* p, int L, int64_t B, int* waves, int* split_f32,
-                   int* split_bf16) {
+int bh_plan_set_tuning(bh_plan* p, int L, int waves, int persistent) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (L < 0 || L > p->L_max) return set_error(BH_EINVAL, "L outside 0..L_max");
+  if (waves != 0 && waves != 4 && waves != 5 && waves != 6 && waves != 8 && waves != 10 &&
+      waves != 12 && waves != 16)
+    return set_error(BH_EINVAL, "wave count must be 0 or one of 4, 5, 6, 8, 10, 12, 16");
+  if (waves > 2 * L + 1 && waves > 4) return set_error(BH_EINVAL, "more waves than p-groups");
+  p->tuned_waves[L] = waves;
+  p->tuned_persist[L] = persistent ? 1 : 0;
+  return BH_OK;
+}
+
+int bh_plan_tuning(const bh_plan* p, int L, int64_t B, int* waves, int* persistent,
+                   int* split_f32, int* split_bf16) {
   if (!p) return set_error(BH_EINVAL, "plan is NULL");
   if (L < 0 || L > p->L_max) return set_error(BH_EINVAL, "L outside 0..L_max");
   if (B < 1) return set_error(BH_EINVAL, "batch size out of range");
   if (waves) *waves = p->tuned_waves[L];
+  if (persistent) *persistent = p->tuned_persist[L];
   const int64_t mt = (B + kGemmBM - 1) / kGemmBM;
   const int64_t nt = p->C_pad / kGemmBN, nk = p->V_pad / kGemmBK;
   if (split_f32) *split_f32 = expand_split(mt, nt, nk, false, &p->tuned_split[0]);

@@ -95,6 +95,7 @@ struct bh_plan {
   bh::Profiler prof;
   // autotuned launch shapes (0 / absent: the built-in rules)
   int tuned_waves[BH_MAX_L + 1] = {};
+  int tuned_persist[BH_MAX_L + 1] = {};   // 1: ascent launches as resident workgroups only
   std::map<int64_t, int> tuned_split[2];   // particle tiles -> split-K (FP32, BF16 GEMM)
 };
 

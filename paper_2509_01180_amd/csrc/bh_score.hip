@@ -27,6 +27,8 @@
 #include "bh_internal.h"
 
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <string>
 
 namespace bh {
@@ -316,99 +318,105 @@ __global__ __launch_bounds__(64 * W) BH_MARCH_OCCUPANCY(NEWTON, G < 64) void k_m
   __shared__ double st[NS * 64];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int64_t pb, r;
-  if constexpr (G == 64) {
-    pb = blockIdx.y;
-    r = (int64_t)blockIdx.x * 64 + lane;
-  } else {
-    pb = (int64_t)blockIdx.y * (64 / G) + lane / G;
-    r = lane % G;
-  }
-  const bool active = pb < B && r < P;
-  if (pb >= B) pb = B - 1;          // idle lanes read a valid particle
-  const double* Xp = X + pb * n_entries * 4;
-  const double wb = Wb[pb];
-  const double eta0 = (wb > 0.0) ? step_init / wb : 0.0;
-  if (wave == 0) {
-    double xa = 0.0, xb = 0.0, xg = 0.0;
-    if (active) {
-      const double* s0 = state + (pb * P + r) * 3;
-      xa = s0[0];
-      xb = s0[1];
-      xg = s0[2];
+  // Particles are taken in a grid-stride loop over blockIdx.y: one pass when
+  // the grid covers the batch, persistent workgroups when it is smaller.
+  constexpr int64_t PER = (G == 64) ? 1 : 64 / G;
+  for (int64_t base = blockIdx.y; base * PER < B; base += gridDim.y) {
+    int64_t pb, r;
+    if constexpr (G == 64) {
+      pb = base;
+      r = (int64_t)blockIdx.x * 64 + lane;
+    } else {
+      pb = base * PER + lane / G;
+      r = lane % G;
     }
-    wrap_euler(xa, xb, xg);
-    st[ST_TA * 64 + lane] = xa;
-    st[ST_TB * 64 + lane] = xb;
-    st[ST_TG * 64 + lane] = xg;
-    st[ST_ETA * 64 + lane] = NEWTON ? 1.0 : eta0;
-  }
-  __syncthreads();
-  for (int t = 0; t <= steps; ++t) {
-    const Angles A = prep(st[ST_TA * 64 + lane], st[ST_TB * 64 + lane], st[ST_TG * 64 + lane]);
-    const Acc mine = eval_wave<NEWTON>(A, wave_p + wave * (2 * L + 2), L, p_first, rec, Xp);
-    store_partials<NV>(mine, red, wave, lane);
-    __syncthreads();
+    const bool active = pb < B && r < P;
+    if (pb >= B) pb = B - 1;          // idle lanes read a valid particle
+    const double* Xp = X + pb * n_entries * 4;
+    const double wb = Wb[pb];
+    const double eta0 = (wb > 0.0) ? step_init / wb : 0.0;
     if (wave == 0) {
-      const Acc tr = sum_partials<NV>(red, lane, W);
-      double eta = st[ST_ETA * 64 + lane];
-      // t == 0: the carried point itself; later: accept if not worse
-      const bool take = (t == 0) || (tr.S >= st[ST_S * 64 + lane]);
-      if (take) {
-        st[ST_XA * 64 + lane] = st[ST_TA * 64 + lane];
-        st[ST_XB * 64 + lane] = st[ST_TB * 64 + lane];
-        st[ST_XG * 64 + lane] = st[ST_TG * 64 + lane];
-        st[ST_S * 64 + lane] = tr.S;
-        st[ST_GA * 64 + lane] = tr.ga;
-        st[ST_GB * 64 + lane] = tr.gb;
-        st[ST_GG * 64 + lane] = tr.gg;
-        if constexpr (NEWTON) {
-          st[ST_HAA * 64 + lane] = tr.haa;
-          st[ST_HAB * 64 + lane] = tr.hab;
-          st[ST_HAG * 64 + lane] = tr.hag;
-          st[ST_HBB * 64 + lane] = tr.hbb;
-          st[ST_HBG * 64 + lane] = tr.hbg;
-          st[ST_HGG * 64 + lane] = tr.hgg;
-        }
+      double xa = 0.0, xb = 0.0, xg = 0.0;
+      if (active) {
+        const double* s0 = state + (pb * P + r) * 3;
+        xa = s0[0];
+        xb = s0[1];
+        xg = s0[2];
       }
-      if (t > 0) {
-        if (NEWTON)
-          eta = take ? fmin(1.0, eta * grow) : eta * shrink;
-        else
-          eta *= take ? grow : shrink;
-      }
-      st[ST_ETA * 64 + lane] = eta;
-      if (t < steps) {
-        const double xa = st[ST_XA * 64 + lane], xb = st[ST_XB * 64 + lane],
-                     xg = st[ST_XG * 64 + lane];
-        const double ga = st[ST_GA * 64 + lane], gb = st[ST_GB * 64 + lane],
-                     gg = st[ST_GG * 64 + lane];
-        double da, db, dg;
-        if constexpr (NEWTON) {
-          const double h[6] = {st[ST_HAA * 64 + lane], st[ST_HAB * 64 + lane],
-                               st[ST_HAG * 64 + lane], st[ST_HBB * 64 + lane],
-                               st[ST_HBG * 64 + lane], st[ST_HGG * 64 + lane]};
-          newton_direction(xb, ga, gb, gg, h, eta0, da, db, dg);
-        } else {
-          natural_gradient(xb, ga, gb, gg, da, db, dg);
-        }
-        double ta = xa + eta * da;
-        double tb = xb + eta * db;
-        double tg = xg + eta * dg;
-        wrap_euler(ta, tb, tg);
-        st[ST_TA * 64 + lane] = ta;
-        st[ST_TB * 64 + lane] = tb;
-        st[ST_TG * 64 + lane] = tg;
-      }
+      wrap_euler(xa, xb, xg);
+      st[ST_TA * 64 + lane] = xa;
+      st[ST_TB * 64 + lane] = xb;
+      st[ST_TG * 64 + lane] = xg;
+      st[ST_ETA * 64 + lane] = NEWTON ? 1.0 : eta0;
     }
     __syncthreads();
-  }
-  if (wave == 0 && active) {
-    double* so = state + (pb * P + r) * 3;
-    so[0] = st[ST_XA * 64 + lane];
-    so[1] = st[ST_XB * 64 + lane];
-    so[2] = st[ST_XG * 64 + lane];
-    sscore[pb * P + r] = st[ST_S * 64 + lane];
+    for (int t = 0; t <= steps; ++t) {
+      const Angles A = prep(st[ST_TA * 64 + lane], st[ST_TB * 64 + lane], st[ST_TG * 64 + lane]);
+      const Acc mine = eval_wave<NEWTON>(A, wave_p + wave * (2 * L + 2), L, p_first, rec, Xp);
+      store_partials<NV>(mine, red, wave, lane);
+      __syncthreads();
+      if (wave == 0) {
+        const Acc tr = sum_partials<NV>(red, lane, W);
+        double eta = st[ST_ETA * 64 + lane];
+        // t == 0: the carried point itself; later: accept if not worse
+        const bool take = (t == 0) || (tr.S >= st[ST_S * 64 + lane]);
+        if (take) {
+          st[ST_XA * 64 + lane] = st[ST_TA * 64 + lane];
+          st[ST_XB * 64 + lane] = st[ST_TB * 64 + lane];
+          st[ST_XG * 64 + lane] = st[ST_TG * 64 + lane];
+          st[ST_S * 64 + lane] = tr.S;
+          st[ST_GA * 64 + lane] = tr.ga;
+          st[ST_GB * 64 + lane] = tr.gb;
+          st[ST_GG * 64 + lane] = tr.gg;
+          if constexpr (NEWTON) {
+            st[ST_HAA * 64 + lane] = tr.haa;
+            st[ST_HAB * 64 + lane] = tr.hab;
+            st[ST_HAG * 64 + lane] = tr.hag;
+            st[ST_HBB * 64 + lane] = tr.hbb;
+            st[ST_HBG * 64 + lane] = tr.hbg;
+            st[ST_HGG * 64 + lane] = tr.hgg;
+          }
+        }
+        if (t > 0) {
+          if (NEWTON)
+            eta = take ? fmin(1.0, eta * grow) : eta * shrink;
+          else
+            eta *= take ? grow : shrink;
+        }
+        st[ST_ETA * 64 + lane] = eta;
+        if (t < steps) {
+          const double xa = st[ST_XA * 64 + lane], xb = st[ST_XB * 64 + lane],
+                       xg = st[ST_XG * 64 + lane];
+          const double ga = st[ST_GA * 64 + lane], gb = st[ST_GB * 64 + lane],
+                       gg = st[ST_GG * 64 + lane];
+          double da, db, dg;
+          if constexpr (NEWTON) {
+            const double h[6] = {st[ST_HAA * 64 + lane], st[ST_HAB * 64 + lane],
+                                 st[ST_HAG * 64 + lane], st[ST_HBB * 64 + lane],
+                                 st[ST_HBG * 64 + lane], st[ST_HGG * 64 + lane]};
+            newton_direction(xb, ga, gb, gg, h, eta0, da, db, dg);
+          } else {
+            natural_gradient(xb, ga, gb, gg, da, db, dg);
+          }
+          double ta = xa + eta * da;
+          double tb = xb + eta * db;
+          double tg = xg + eta * dg;
+          wrap_euler(ta, tb, tg);
+          st[ST_TA * 64 + lane] = ta;
+          st[ST_TB * 64 + lane] = tb;
+          st[ST_TG * 64 + lane] = tg;
+        }
+      }
+      __syncthreads();
+    }
+    if (wave == 0 && active) {
+      double* so = state + (pb * P + r) * 3;
+      so[0] = st[ST_XA * 64 + lane];
+      so[1] = st[ST_XB * 64 + lane];
+      so[2] = st[ST_XG * 64 + lane];
+      sscore[pb * P + r] = st[ST_S * 64 + lane];
+    }
+    __syncthreads();   // the next particle's set-up overwrites the ascent state
   }
 }
 
@@ -641,13 +649,35 @@ void launch_correlate_any(int W, bh_plan* p, dim3 grid, hipStream_t s, const Dev
   }
 }
 
+// Workgroups of a kernel that fit on the device at once (0 if unknown),
+// cached per kernel.
+template <typename K>
+int64_t resident_workgroups(K kernel, int threads) {
+  static std::mutex mu;
+  static std::map<const void*, int64_t> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = cache.find((const void*)kernel);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return cache[(const void*)kernel] = (int64_t)per_cu * cus;
+}
+
 template <int W, bool NEWTON, int G>
 void launch_march_w(bh_plan* p, int64_t B, hipStream_t s, const DevBand& band, const double* X,
                     const double* Wb, int P, int steps, const bh_align_opts& o, double* state,
                     double* sscore) {
   const int L = band.L;
-  const dim3 grid = (G == 64) ? dim3((unsigned)((P + 63) / 64), (unsigned)B)
-                              : dim3(1u, (unsigned)((B + 64 / G - 1) / (64 / G)));
+  int64_t ny = (G == 64) ? B : (B + 64 / G - 1) / (64 / G);
+  const int64_t nx = (G == 64) ? (P + 63) / 64 : 1;
+  if (p->tuned_persist[L]) {   // persistent: only as many workgroups as are resident
+    const int64_t cap = resident_workgroups(k_march<W, NEWTON, G>, 64 * W) / nx;
+    if (cap > 0 && cap < ny) ny = cap;
+  }
+  const dim3 grid((unsigned)nx, (unsigned)ny);
   ProfScope ps(p, (NEWTON ? "newton_L" : "march_L") + std::to_string(L), s,
                B * P * (int64_t)(steps + 1) * band.n_entries);
   hipLaunchKernelGGL((k_march<W, NEWTON, G>), grid, dim3(64 * W), 0, s, band.p_first,
@@ -910,7 +940,22 @@ int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, 
         best_w = W;
       }
     }
-    if (rc == BH_OK) p->tuned_waves[band->L] = best_w;
+    if (rc != BH_OK) break;
+    // the best wave count again with persistent workgroups
+    p->tuned_persist[band->L] = 1;
+    float pms = 0.0f;
+    for (int rep = 0; rep < 3; ++rep) {
+      hipMemcpyAsync(state, starts, (size_t)ns * sizeof(double), hipMemcpyDeviceToDevice, s);
+      hipEventRecord(e0, s);
+      launch_march_any<false>(best_w, 64, p, B, s, *band, X, Wb, P, 2, o, state, sscore);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float t = 0.0f;
+      hipEventElapsedTime(&t, e0, e1);
+      if (rep > 0) pms += t;
+    }
+    p->tuned_persist[band->L] = (pms < 0.99f * best_ms) ? 1 : 0;
+    p->tuned_waves[band->L] = best_w;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

@@ -29,7 +29,7 @@ def test_autotune_choices_and_results():
     a0 = plan.expand(v)
     e0, s0 = plan.align(a0, b.contiguous(), (8, 16), starts, 10)
     before = plan.tuning(B, (8, 16))
-    assert before["waves"] == {8: 0, 16: 0}
+    assert before["waves"] == {8: 0, 16: 0} and before["persistent"] == {8: 0, 16: 0}
     got = plan.autotune(B, (8, 16), restarts=P)
     print("tuned", got)
     assert all(w in (4, 5, 6, 8, 10, 12, 16) for w in got["waves"].values())
@@ -40,4 +40,39 @@ def test_autotune_choices_and_results():
     assert np.all(normwise(to_complex(a1), to_complex(a0)) <= 1e-6)
     s0, s1 = s0.cpu().numpy(), s1.cpu().numpy()
     assert np.max(np.abs(s1 - s0) / np.abs(s0)) <= 1e-6
+    plan.close()
+
+
+def test_persistent_launches_match():
+    """Persistent workgroups (fewer than the particles, looping) give the
+    same bits as one workgroup per particle with the same wave count."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd._lib import BhError
+    dev = cuda_device()
+    N, L, B, P = 20, 12, 1200, 64
+    rng = np.random.default_rng(9)
+    bl = synth.blob_template(rng, 12)
+    vols = np.stack([synth.render_blobs(bl, N, g) for g in
+                     synth.quat_to_matrix(synth.haar_quaternions(rng, B))]).astype(np.float32)
+    starts = torch.from_numpy(synth.matrix_to_euler_zyz(synth.quat_to_matrix(
+        synth.haar_quaternions(rng, B * P))).reshape(B, P, 3)).to(dev)
+    say(f"persistent march N={N} L={L} B={B}")
+    plan = Plan(N, L, device=0)
+    b = plan.expand(torch.from_numpy(synth.render_blobs(bl, N)[None].astype(np.float32)).to(dev))[0]
+    a = plan.expand(torch.from_numpy(vols).to(dev))
+    for Lb in (6, 12):
+        plan.set_tuning(Lb, 12, False)
+    ref = plan.align(a, b.contiguous(), (6, 12), starts, 5, return_all=True)
+    for Lb in (6, 12):
+        plan.set_tuning(Lb, 12, True)
+    got = plan.align(a, b.contiguous(), (6, 12), starts, 5, return_all=True)
+    torch.cuda.synchronize()
+    for x, y in zip(ref, got):
+        assert torch.equal(x, y)
+    assert plan.tuning(B, (6, 12))["persistent"] == {6: 1, 12: 1}
+    with pytest.raises(BhError):
+        plan.set_tuning(2, 12, False)      # more waves than p-groups at L = 2
+    with pytest.raises(BhError):
+        plan.set_tuning(6, 7, False)
     plan.close()
