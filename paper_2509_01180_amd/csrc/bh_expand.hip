@@ -258,32 +258,24 @@ int tune_expand_f32(bh_plan* p, int64_t B, hipStream_t s) {
   // timing data: the basis itself stands in for the volumes (any finite values)
   BH_HIP(hipMemcpyAsync(Ft, p->psi, (size_t)p->V_pad * std::min(M_pad, p->C_pad) * sizeof(float),
                         hipMemcpyDeviceToDevice, s));
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
   float best_ms = 1e30f;
   int best = 1;
   for (int ns = 1; ns <= 16; ns *= 2) {
     if (nk_total / ns < 8) break;
     float ms = 0.0f;
-    for (int rep = 0; rep < 3; ++rep) {
-      hipEventRecord(e0, s);
-      hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)(mt * nt * ns)), dim3(256), 0, s, Ft, p->psi,
-                         part, M_pad, p->C_pad, (int)(nk_total / ns), ns);
-      hipEventRecord(e1, s);
-      hipEventSynchronize(e1);
-      float t = 0.0f;
-      hipEventElapsedTime(&t, e0, e1);
-      if (rep > 0) ms += t;
-    }
+    rc = time_on_stream(
+        s, 2, [] {},
+        [&] {
+          hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)(mt * nt * ns)), dim3(256), 0, s, Ft,
+                             p->psi, part, M_pad, p->C_pad, (int)(nk_total / ns), ns);
+        },
+        &ms);
+    if (rc != BH_OK) return rc;
     if (ms < best_ms) {
       best_ms = ms;
       best = ns;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  BH_HIP(hipGetLastError());
   p->tuned_split[0][mt] = best;
   return BH_OK;
 }

@@ -330,33 +330,26 @@ int tune_expand_bf16(bh_plan* p, int64_t B, hipStream_t s) {
   const size_t n = (size_t)std::min(M_pad, p->C_pad) * p->V_pad * sizeof(uint16_t);
   BH_HIP(hipMemcpyAsync(fh, p->psi_h, n, hipMemcpyDeviceToDevice, s));
   BH_HIP(hipMemcpyAsync(fl, p->psi_l, n, hipMemcpyDeviceToDevice, s));
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
   float best_ms = 1e30f;
   int best = 1;
   for (int ns = 1; ns <= 16; ns *= 2) {
     if (nk_total / ns < 8) break;
     float ms = 0.0f;
-    for (int rep = 0; rep < 3; ++rep) {
-      hipEventRecord(e0, s);
-      hipLaunchKernelGGL((k_gemm_bf16<true, true>), dim3((unsigned)(mt * nt * ns)), dim3(256), 0, s,
-                         fh, fl, p->psi_h, p->psi_l, part, part + (size_t)ns * M_pad * p->C_pad,
-                         M_pad, p->C_pad, p->V_pad, (int)(nk_total / ns), ns);
-      hipEventRecord(e1, s);
-      hipEventSynchronize(e1);
-      float t = 0.0f;
-      hipEventElapsedTime(&t, e0, e1);
-      if (rep > 0) ms += t;
-    }
+    rc = time_on_stream(
+        s, 2, [] {},
+        [&] {
+          hipLaunchKernelGGL((k_gemm_bf16<true, true>), dim3((unsigned)(mt * nt * ns)), dim3(256),
+                             0, s, fh, fl, p->psi_h, p->psi_l, part,
+                             part + (size_t)ns * M_pad * p->C_pad, M_pad, p->C_pad, p->V_pad,
+                             (int)(nk_total / ns), ns);
+        },
+        &ms);
+    if (rc != BH_OK) return rc;
     if (ms < best_ms) {
       best_ms = ms;
       best = ns;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  BH_HIP(hipGetLastError());
   p->tuned_split[1][mt] = best;
   return BH_OK;
 }

@@ -158,6 +158,35 @@ int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const floa
 int launch_degree_energy(bh_plan* p, const DevBand& band, const float* a, const float* b,
                          const int32_t* tmpl, int n_tmpl, int64_t B, double* energy,
                          hipStream_t s);
+// Milliseconds of `launch` on stream s (HIP events), summed over `reps` runs
+// after one warm-up run; `prepare` is enqueued before each run, untimed.
+template <typename Prep, typename Launch>
+int time_on_stream(hipStream_t s, int reps, Prep&& prepare, Launch&& launch, float* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return set_error(BH_EDEVICE, "hipEventCreate failed");
+  }
+  float total = 0.0f;
+  hipError_t e = hipSuccess;
+  for (int rep = 0; rep <= reps && e == hipSuccess; ++rep) {
+    prepare();
+    if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+    launch();
+    if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+      break;
+    float t = 0.0f;
+    if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) break;
+    if (rep > 0) total += t;
+    e = hipGetLastError();
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return set_error(BH_EDEVICE, std::string("timing: ") + hipGetErrorString(e));
+  *ms = total;
+  return BH_OK;
+}
+
 // Autotuning (see bh_plan_autotune): time the candidate shapes on random
 // data of B particles and record the fastest in the plan.
 int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, hipStream_t s);

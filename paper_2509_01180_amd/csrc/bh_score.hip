@@ -883,7 +883,7 @@ int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, 
   double* starts = nullptr;
   if (hipMalloc((void**)&buf, (size_t)(na + nb + ns) * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&starts, (size_t)ns * sizeof(double)) != hipSuccess) {
-    hipFree(buf);
+    (void)hipFree(buf);
     return set_error(BH_ENOMEM, "autotune buffers");
   }
   float* a = buf;
@@ -895,8 +895,8 @@ int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, 
   int rc = BH_OK;
   if ((rc = grow(p->state_scr, (size_t)B * P * 4 * sizeof(double))) != BH_OK ||
       (rc = grow(p->misc_scr, (size_t)B * sizeof(double))) != BH_OK) {
-    hipFree(buf);
-    hipFree(starts);
+    (void)hipFree(buf);
+    (void)hipFree(starts);
     return rc;
   }
   double* state = (double*)p->state_scr.ptr;
@@ -906,9 +906,9 @@ int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, 
   o.step_init = 1.0;
   o.step_grow = 1.25;
   o.step_shrink = 0.5;
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  auto reset = [&] {
+    (void)hipMemcpyAsync(state, starts, (size_t)ns * sizeof(double), hipMemcpyDeviceToDevice, s);
+  };
   for (int bi = 0; bi < n_bands && rc == BH_OK; ++bi) {
     const DevBand* band = nullptr;
     if ((rc = get_band(p, bands[bi], &band)) != BH_OK) break;
@@ -918,23 +918,15 @@ int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, 
                        nullptr, 1, band->L, band->deg_start, band->deg_off, Wb);
     float best_ms = 1e30f;
     int best_w = 0;
+    p->tuned_persist[band->L] = 0;
     for (int W : {4, 5, 6, 8, 10, 12, 16}) {
       if (W > 2 * band->L + 1 && W > 4) continue;
       float ms = 0.0f;
-      for (int rep = 0; rep < 3; ++rep) {   // the first run warms up
-        hipMemcpyAsync(state, starts, (size_t)ns * sizeof(double), hipMemcpyDeviceToDevice, s);
-        hipEventRecord(e0, s);
-        launch_march_any<false>(W, 64, p, B, s, *band, X, Wb, P, 2, o, state, sscore);
-        hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
-        float t = 0.0f;
-        hipEventElapsedTime(&t, e0, e1);
-        if (rep > 0) ms += t;
-      }
-      if (hipGetLastError() != hipSuccess) {
-        rc = set_error(BH_EDEVICE, "autotune launch failed");
-        break;
-      }
+      rc = time_on_stream(
+          s, 2, reset,
+          [&] { launch_march_any<false>(W, 64, p, B, s, *band, X, Wb, P, 2, o, state, sscore); },
+          &ms);
+      if (rc != BH_OK) break;
       if (ms < best_ms) {
         best_ms = ms;
         best_w = W;
@@ -944,24 +936,17 @@ int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, 
     // the best wave count again with persistent workgroups
     p->tuned_persist[band->L] = 1;
     float pms = 0.0f;
-    for (int rep = 0; rep < 3; ++rep) {
-      hipMemcpyAsync(state, starts, (size_t)ns * sizeof(double), hipMemcpyDeviceToDevice, s);
-      hipEventRecord(e0, s);
-      launch_march_any<false>(best_w, 64, p, B, s, *band, X, Wb, P, 2, o, state, sscore);
-      hipEventRecord(e1, s);
-      hipEventSynchronize(e1);
-      float t = 0.0f;
-      hipEventElapsedTime(&t, e0, e1);
-      if (rep > 0) pms += t;
-    }
+    rc = time_on_stream(
+        s, 2, reset,
+        [&] { launch_march_any<false>(best_w, 64, p, B, s, *band, X, Wb, P, 2, o, state, sscore); },
+        &pms);
+    if (rc != BH_OK) break;
     p->tuned_persist[band->L] = (pms < 0.99f * best_ms) ? 1 : 0;
     p->tuned_waves[band->L] = best_w;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipStreamSynchronize(s);
-  hipFree(buf);
-  hipFree(starts);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  (void)hipFree(starts);
   return rc;
 }
 
