@@ -548,6 +548,8 @@ def uneven_bench(args):
 
 SERVE_PLANS = {32: (16, (8, 16)), 48: (24, (8, 16, 24)), 64: (32, (8, 16, 24, 32)),
                96: (40, (8, 16, 24, 32, 40))}
+# the paper procedure's bands per box edge (energy-ratio choice on the templates: 6 and 11, then L)
+SERVE_PAPER_BANDS = {32: (6, 11, 16), 48: (6, 11, 24), 64: (6, 11, 32), 96: (6, 11, 40)}
 
 
 def serve_bench(args):
@@ -590,9 +592,14 @@ def serve_bench(args):
     t_plan = time.perf_counter() - t_plan
     print(f"# plans built in {t_plan:.1f} s", file=sys.stderr, flush=True)
 
-    eng = Engine({N: SERVE_PLANS[N] for N in boxes}, tmpls, restarts=P, steps=T,
+    if args.method == "paper":
+        boxes_cfg = {N: (SERVE_PLANS[N][0], SERVE_PAPER_BANDS[N]) for N in boxes}
+    else:
+        boxes_cfg = {N: SERVE_PLANS[N] for N in boxes}
+    eng = Engine(boxes_cfg, tmpls, restarts=P, steps=T,
                  budget_bytes=int(args.budget_gib * (1 << 30)), max_cohort=args.max_cohort,
-                 plans=plans)
+                 plans=plans, method=args.method, keep=args.keep,
+                 newton_steps=args.newton_steps)
 
     def make_request(spec, arrival=None):
         # the index tensors are made inside the callables, which the engine
@@ -671,7 +678,7 @@ def serve_bench(args):
             ang.append(np.degrees(2 * np.arcsin(np.minimum(1.0, d / (2 * np.sqrt(2))))))
         ang = np.concatenate(ang) if ang else np.zeros(0)
         per_box[str(N)] = {
-            "L_max": SERVE_PLANS[N][0], "bands": list(SERVE_PLANS[N][1]),
+            "L_max": SERVE_PLANS[N][0], "bands": list(boxes_cfg[N][1]),
             "offered_per_s": round(sum(r.n for r in reqs if r.box == N) / args.duration, 1),
             "sustained_per_s": round(sum(r.n for r in rs) / span, 1),
             "latency": latency_summary([r for r in rs if r.arrival >= t0 + warm]),
@@ -718,7 +725,11 @@ def serve_bench(args):
         "config": {
             "workload": f"Poisson {args.rate}/s requests of U{{1..512}} subtomograms, boxes {boxes}, "
                         f"8 resident templates (30-80 blobs), +/-60 deg wedge, SNR 0.05, "
-                        f"64 restarts, 20 steps/band",
+                        f"64 restarts, 20 steps/band"
+                        + ("" if args.method == "march" else
+                           f"; paper procedure: {args.keep} candidates after the lowest band, "
+                           f"{args.newton_steps} Newton steps per higher band"),
+            "method": args.method,
             "duration_s": args.duration, "warmup_excluded_s": warm,
             "budget_gib": args.budget_gib, "max_cohort": args.max_cohort,
             "parallelism": "single GPU",

@@ -171,6 +171,15 @@ int bh_correlate_hess(bh_plan* p, const float* a, const float* b, int64_t B, int
                       const double* euler, int R, double* score, double* grad, double* hess,
                       void* stream);
 
+/* Candidate selection on its own (the rule of n_keep above), e.g. between
+ * single-band calls: from every particle's P restarts (P <= 1024) keep K
+ * (1 <= K <= min(64, P)) in the order taken.
+ * euler: dev double[B][P][3], score: dev double[B][P];
+ * euler_out: dev double[B][K][3], score_out: dev double[B][K]. */
+int bh_prune_candidates(bh_plan* p, const double* euler, const double* score, int64_t B, int P,
+                        int K, double min_sep, double* euler_out, double* score_out,
+                        void* stream);
+
 /* ---------------------------------------------------------------------
  * Degree energies of the band-L cross-power (Sec. II-C, energy ratio):
  * energy[b][l] = ||xi^l||_F^2 = sum_{m,n} |xi^l_{mn}|^2, l = 0..L.

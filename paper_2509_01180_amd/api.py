@@ -290,6 +290,24 @@ class Plan:
         idx = torch.tensor([[0, 1, 2], [1, 3, 4], [2, 4, 5]], device=a.device)
         return score, g, h6[:, :, idx]
 
+    def prune(self, euler: torch.Tensor, score: torch.Tensor, K: int, min_sep: float,
+              out: tuple | None = None):
+        """K candidates per particle from euler [B, P, 3] / score [B, P]
+        (see bh_prune_candidates): (euler [B, K, 3], score [B, K])."""
+        B, P = score.shape
+        _dev(euler, torch.float64, (B, P, 3), "euler")
+        _dev(score, torch.float64, (B, P), "score")
+        if out is None:
+            out = (torch.empty((B, K, 3), dtype=torch.float64, device=euler.device),
+                   torch.empty((B, K), dtype=torch.float64, device=euler.device))
+        eo, so = out
+        _dev(eo, torch.float64, (B, K, 3), "euler_out")
+        _dev(so, torch.float64, (B, K), "score_out")
+        check(lib().bh_prune_candidates(self._h, _ptr(euler), _ptr(score), B, P, int(K),
+                                        float(min_sep), _ptr(eo), _ptr(so), _stream()),
+              "bh_prune_candidates")
+        return eo, so
+
     def degree_energy(self, a: torch.Tensor, b: torch.Tensor, L: int) -> torch.Tensor:
         """||xi^l||_F^2 of the band-L cross-power, [B, L+1] float64."""
         B = a.shape[0]

@@ -579,6 +579,25 @@ int bh_align_uneven(bh_plan* p, const float* a, int64_t lda, const int32_t* Lp,
   });
 }
 
+int bh_prune_candidates(bh_plan* p, const double* euler, const double* score, int64_t B, int P,
+                        int K, double min_sep, double* euler_out, double* score_out,
+                        void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
+  if (P < 1 || P > kPruneMaxP) return set_error(BH_EINVAL, "restart count outside 1..1024");
+  if (K < 1 || K > 64 || K > P) return set_error(BH_EINVAL, "K outside 1..min(64, P)");
+  if (!(min_sep >= 0.0) || min_sep > 3.141592653589793)
+    return set_error(BH_EINVAL, "min_sep outside [0, pi]");
+  if (B == 0) return BH_OK;
+  if (!euler || !score || !euler_out || !score_out) return set_error(BH_EINVAL, "NULL buffer");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    return launch_prune(p, euler, score, B, P, K, min_sep, euler_out, score_out,
+                        (hipStream_t)stream);
+  });
+}
+
 int bh_align(bh_plan* p, const float* a, const float* b, int64_t B, const bh_align_opts* o,
              const double* starts, double* euler_out, double* score_out, double* all_euler,
              double* all_score, void* stream) {

@@ -192,6 +192,8 @@ int time_on_stream(hipStream_t s, int reps, Prep&& prepare, Launch&& launch, flo
 int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, hipStream_t s);
 int tune_expand_f32(bh_plan* p, int64_t B, hipStream_t s);
 int tune_expand_bf16(bh_plan* p, int64_t B, hipStream_t s);
+int launch_prune(bh_plan* p, const double* euler, const double* score, int64_t B, int P, int K,
+                 double min_sep, double* euler_out, double* score_out, hipStream_t s);
 int launch_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shifts_host,
                         int S, const float* b, const bh_align_opts& o, const double* starts,
                         double* euler_out, double* score_out, int32_t* shift_out, hipStream_t s);

@@ -950,6 +950,17 @@ int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, 
   return rc;
 }
 
+int launch_prune(bh_plan* p, const double* euler, const double* score, int64_t B, int P, int K,
+                 double min_sep, double* euler_out, double* score_out, hipStream_t s) {
+  const double half = 0.5 * min_sep;
+  const double thr = 4.0 * sin(half) * sin(half);
+  ProfScope ps(p, "prune", s, B);
+  hipLaunchKernelGGL(k_prune, dim3((unsigned)B), dim3(64), 0, s, euler, score, P, K, thr,
+                     euler_out, score_out);
+  BH_HIP(hipGetLastError());
+  return BH_OK;
+}
+
 int launch_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shifts_host,
                         int S, const float* b, const bh_align_opts& o, const double* starts,
                         double* euler_out, double* score_out, int32_t* shift_out,

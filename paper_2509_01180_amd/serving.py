@@ -177,9 +177,17 @@ class Engine:
     def __init__(self, boxes: dict, templates: dict, restarts: int, steps: int,
                  budget_bytes: int = 24 << 30, max_cohort: int = 2048, device: int = 0,
                  step_init: float = 1.0, step_grow: float = 1.25, step_shrink: float = 0.5,
-                 plans: dict | None = None):
+                 plans: dict | None = None, method: str = "march", keep: int = 8,
+                 min_sep: float = 0.17453292519943295, newton_steps: int = 6):
+        """method "march": gradient steps on every band; "paper": after the
+        first band only `keep` candidates (local maxima at least `min_sep`
+        radians apart) continue, with `newton_steps` Newton steps per band."""
         import torch
         from .api import Plan
+        if method not in ("march", "paper"):
+            raise ValueError("method is 'march' or 'paper'")
+        self.method, self.keep, self.min_sep = method, int(keep), float(min_sep)
+        self.newton_steps = int(newton_steps)
         self.torch = torch
         self.dev = torch.device("cuda", device)
         self.P, self.steps = int(restarts), int(steps)
@@ -305,15 +313,31 @@ class Engine:
                                    for r in c.requests])
             d["euler"] = torch.empty((c.n, 3), dtype=torch.float64, device=self.dev)
             d["score"] = torch.empty((c.n,), dtype=torch.float64, device=self.dev)
+            if self.method == "paper":
+                d["all_score"] = torch.empty((c.n, self.P), dtype=torch.float64, device=self.dev)
 
     def _band(self, c: Cohort, band: int, last: bool) -> None:
         torch = self.torch
         plan, s, d = self.plans[c.box], self.streams[c.box], c.dev
         with torch.cuda.stream(s):
             a = d["a"] if last else d["a_bf16"]
-            plan.align_t(a, self.templates[c.box], d["tmpl"], [band], d["state"], self.steps,
-                         *self.step_args, out=(d["euler"], d["score"], d["state"], None),
-                         batch_invariant=True)
+            if self.method == "march":
+                plan.align_t(a, self.templates[c.box], d["tmpl"], [band], d["state"], self.steps,
+                             *self.step_args, out=(d["euler"], d["score"], d["state"], None),
+                             batch_invariant=True)
+            elif c.cursor == 0:
+                # lowest band: all starts, then the best distinct local maxima
+                plan.align_t(a, self.templates[c.box], d["tmpl"], [band], d["state"], self.steps,
+                             *self.step_args, out=(d["euler"], d["score"], d["state"], d["all_score"]),
+                             batch_invariant=True)
+                k = min(self.keep, self.P)
+                d["state"], _sc = plan.prune(d["state"], d["all_score"], k, self.min_sep)
+                del d["all_score"]
+            else:
+                plan.align_t(a, self.templates[c.box], d["tmpl"], [band], d["state"],
+                             self.steps, *self.step_args,
+                             out=(d["euler"], d["score"], d["state"], None), batch_invariant=True,
+                             newton_bands=1, newton_steps=self.newton_steps)
 
     def _finish(self, c: Cohort) -> None:
         torch = self.torch

@@ -156,3 +156,30 @@ def test_keep_edge_cases():
     with pytest.raises(BhError):
         plan.align(da, db, (4, 8), big, 3, keep=4)
     plan.close()
+
+
+def test_prune_candidates_vs_oracle():
+    """bh_prune_candidates against the oracle's rule on restarts with tied
+    scores, exact duplicate rotations and near neighbours."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    dev = cuda_device()
+    rng = np.random.default_rng(51)
+    B, P, K = 5, 40, 8
+    sep = np.radians(10.0)
+    E = synth.matrix_to_euler_zyz(synth.quat_to_matrix(synth.haar_quaternions(rng, B * P)))
+    E = E.reshape(B, P, 3)
+    S = np.round(rng.uniform(0, 5, (B, P)), 1)            # many ties
+    E[:, 5] = E[:, 3]                                      # duplicates
+    E[:, 7] = E[:, 2] + np.array([0.02, 0.01, -0.02])     # a near neighbour (~2 degrees)
+    S[:, 7] = S[:, 2]
+    say(f"prune_candidates B={B} P={P} K={K}")
+    plan = Plan(16, 4, device=0)
+    eo, so = plan.prune(torch.from_numpy(E).to(dev), torch.from_numpy(S).to(dev), K, sep)
+    torch.cuda.synchronize()
+    eo, so = eo.cpu().numpy(), so.cpu().numpy()
+    plan.close()
+    for i in range(B):
+        sel = oalign.prune_candidates(E[i], S[i], K, sep)
+        np.testing.assert_array_equal(eo[i], E[i][sel])
+        np.testing.assert_array_equal(so[i], S[i][sel])

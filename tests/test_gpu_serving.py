@@ -67,6 +67,12 @@ def test_align_t_equals_single_template_align():
             rows = torch.from_numpy(np.nonzero(tid == t)[0]).to(dev)
             for x, y in zip(mix, one):
                 assert torch.equal(x[rows], y[rows])
+    # template indices outside the table are clamped to its ends
+    wild = torch.from_numpy(np.where(tid == 0, -3, np.where(tid == T_RES - 1, T_RES + 5, tid))
+                            .astype(np.int32)).to(dev)
+    mix = plan.align_t(a, tmpl, ti, (5, 10), starts, STEPS, batch_invariant=True)
+    clamped = plan.align_t(a, tmpl, wild, (5, 10), starts, STEPS, batch_invariant=True)
+    assert torch.equal(mix[0], clamped[0]) and torch.equal(mix[1], clamped[1])
     # a one-entry table with no index is the one-template case
     e1 = plan.align_t(a, tmpl[:1].contiguous(), None, (5, 10), starts, STEPS)
     e2 = plan.align(a, tmpl[0].contiguous(), (5, 10), starts, STEPS)
@@ -174,3 +180,44 @@ def test_served_result_matches_oracle():
         assert ang <= 1.0 or abs(r.score[i] - s_ref) <= 1e-4 * abs(s_ref)
         assert abs(r.score[i] - s_ref) <= 1e-3 * abs(s_ref)
     plan.close()
+
+
+def test_paper_method_same_alone_and_in_mix():
+    """The paper procedure in the serving loop (candidates after the lowest
+    band, Newton steps on the higher ones): each request's result is the
+    same bits alone and in a mix."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd.serving import Engine, Request
+    dev = cuda_device()
+    boxes = {16: (6, (3, 5, 6)), 24: (10, (4, 7, 10))}
+    plans = {N: Plan(N, L, device=0) for N, (L, _b) in boxes.items()}
+    tmpls, blobs = {}, {}
+    for N in boxes:
+        tmpls[N], blobs[N] = _templates(plans[N], N)
+    rng = np.random.default_rng(12)
+    spec = [(int(rng.choice(list(boxes))), int(rng.integers(T_RES)), int(rng.integers(1, 30)))
+            for _ in range(7)]
+    data = []
+    for i, (N, t, n) in enumerate(spec):
+        v, _g = _particles(blobs[N], N, t, n, 2000 + i)
+        data.append((torch.from_numpy(v).to(dev),
+                     torch.from_numpy(synth.serving.start_pool(n, P, seed=70 + i)).to(dev)))
+    torch.cuda.synchronize()
+    say(f"serving paper method, mix of {len(spec)} requests")
+    kw = dict(restarts=P, steps=STEPS, plans=plans, method="paper", keep=6, newton_steps=4)
+    eng = Engine(boxes, tmpls, max_cohort=40, **kw)
+    reqs = []
+    for i, ((N, t, n), (v, st)) in enumerate(zip(spec, data)):
+        reqs.append(eng.submit(Request(box=N, template=t, n=n, volumes=v, starts=st)))
+        if i % 2 == 1:
+            eng.step()
+    eng.drain()
+    alone = Engine(boxes, tmpls, **kw)
+    for r, (N, t, n), (v, st) in zip(reqs, spec, data):
+        a = alone.submit(Request(box=N, template=t, n=n, volumes=v, starts=st))
+        alone.drain()
+        np.testing.assert_array_equal(a.euler, r.euler)
+        np.testing.assert_array_equal(a.score, r.score)
+    for p in plans.values():
+        p.close()
