@@ -249,7 +249,7 @@ void bh_plan_destroy(bh_plan* p) {
   if (!p) return;
   DeviceGuard g(p->device);
   (void)hipDeviceSynchronize();
-  for (void* q : {(void*)p->psi, (void*)p->psi_h, (void*)p->psi_l, (void*)p->vidx, (void*)p->csrc,
+  for (void* q : {(void*)p->psi, (void*)p->psi_h, (void*)p->psi_l, (void*)p->vrep, (void*)p->csrc,
                   (void*)p->csgn})
     if (q) (void)hipFree(q);
   for (Buffer* b : {&p->gathered, &p->partial, &p->xi_scr, &p->state_scr, &p->misc_scr,
@@ -304,7 +304,7 @@ int bh_plan_tuning(const bh_plan* p, int L, int64_t B, int* waves, int* persiste
   if (waves) *waves = p->tuned_waves[L];
   if (persistent) *persistent = p->tuned_persist[L];
   const int64_t mt = (B + kGemmBM - 1) / kGemmBM;
-  const int64_t nt = p->C_pad / kGemmBN, nk = p->V_pad / kGemmBK;
+  const int64_t nt = p->C_pad / kGemmBN, nk = p->VR_pad / kGemmBK;
   if (split_f32) *split_f32 = expand_split(mt, nt, nk, false, &p->tuned_split[0]);
   if (split_bf16) *split_bf16 = expand_split(mt, nt, nk, false, &p->tuned_split[1]);
   return BH_OK;

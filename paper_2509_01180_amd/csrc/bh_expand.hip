@@ -1,11 +1,17 @@
 // Expansion (Sec. II-A): a[b][c] = sum_v F[b][v] Psi[v][c], the voxel
-// quadrature of <f, psi_klm> as one dense real GEMM on MFMA, then the
-// complex coefficients of every m are rebuilt from the real columns.
+// quadrature of <f, psi_klm> as dense real GEMMs on MFMA, then the complex
+// coefficients of every m are rebuilt from the real columns.
 //
-//   k_gather  : volumes [B][N^3] -> Ft[V_pad][M_pad] (ball voxels, transposed,
-//               zero padded), so both GEMM operands are K-major.
+// The sum runs over orbit representatives of the three coordinate
+// reflections, one GEMM slice per parity class of the columns (the fold is
+// described with ClassTiles).
+//
+//   k_gather  : volumes [B][N^3] -> Ft[8][VR_pad][M_pad]: the 8 signed
+//               mirror sums g_P of each representative, transposed and zero
+//               padded, so both GEMM operands are K-major.
 //   k_gemm_f32: split-K GEMM on v_mfma_f32_32x32x2f32, 128x128 tiles,
-//               K step 32, LDS double buffer; partial sums per split.
+//               K step 32, LDS double buffer; partial sums per split; a
+//               column tile reads the Ft slice of its class.
 //   k_reduce  : sums the splits in a fixed order and writes the complex
 //               layout (re, im) for m = -l..l.
 #include "bh_internal.h"
@@ -19,61 +25,89 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
 
-// Ft[v][b] = vols[b][vidx[v]] (0 outside v < V, b < B).  32x32 LDS transpose.
+// Ft[P][v][b] = g_P of particle b at representative v (0 outside v < VR,
+// b < B).  32x32 LDS transpose per class.
 __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ vols, int64_t vol_stride,
-                                                int64_t B, const int32_t* __restrict__ vidx,
-                                                int64_t V, int64_t M_pad, float* __restrict__ Ft) {
-  __shared__ float tile[32][33];
+                                                int64_t B, const int32_t* __restrict__ vrep,
+                                                int64_t VR, int64_t VR_pad, int64_t M_pad, int N,
+                                                float* __restrict__ Ft) {
+  __shared__ float tile[kParityClasses][32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
   const int64_t v0 = (int64_t)blockIdx.x * 32, b0 = (int64_t)blockIdx.y * 32;
   const int64_t v = v0 + tx;
-  const int32_t lin = (v < V) ? vidx[v] : 0;
+  int32_t off[8];
+  mirror_offsets((v < VR) ? vrep[v] : 0, N, off);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t b = b0 + ty + 8 * i;
-    tile[ty + 8 * i][tx] = (v < V && b < B) ? vols[b * vol_stride + lin] : 0.0f;
+    float f[8];
+    const bool in = v < VR && b < B;
+    const float* vb = vols + (in ? b * vol_stride : 0);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) f[s] = in ? vb[off[s]] : 0.0f;
+    parity_fold(f);
+#pragma unroll
+    for (int c = 0; c < kParityClasses; ++c) tile[c][ty + 8 * i][tx] = f[c];
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t vv = v0 + ty + 8 * i;
-    Ft[vv * M_pad + b0 + tx] = tile[tx][ty + 8 * i];
+  for (int c = 0; c < kParityClasses; ++c) {
+    float* out = Ft + (int64_t)c * VR_pad * M_pad;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t vv = v0 + ty + 8 * i;
+      out[vv * M_pad + b0 + tx] = tile[c][tx][ty + 8 * i];
+    }
   }
 }
 
-// As k_gather for rows r = b * S + s of integer-shifted volumes:
-// Ft[v][r] = f_b at the ball voxel (i, j, k) moved by shift s, i.e.
-// vols[b][i + dx][j + dy][k + dz] (0 where that leaves the box).
+// As k_gather for rows r = b * S + s of integer-shifted volumes: the images
+// are taken of f_b moved by shift s, i.e. vols[b][i + dx][j + dy][k + dz]
+// at image (i, j, k) (0 where that leaves the box).
 __global__ __launch_bounds__(256) void k_gather_shift(const float* __restrict__ vols, int N,
                                                       int64_t rows, int S, ShiftTable shifts,
-                                                      const int32_t* __restrict__ vidx, int64_t V,
-                                                      int64_t M_pad, float* __restrict__ Ft) {
-  __shared__ float tile[32][33];
+                                                      const int32_t* __restrict__ vrep, int64_t VR,
+                                                      int64_t VR_pad, int64_t M_pad,
+                                                      float* __restrict__ Ft) {
+  __shared__ float tile[kParityClasses][32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
   const int64_t v0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
   const int64_t v = v0 + tx;
-  const int32_t lin = (v < V) ? vidx[v] : 0;
+  const int32_t lin = (v < VR) ? vrep[v] : 0;
   const int vi = lin / (N * N), vj = (lin / N) % N, vk = lin % N;
   const int64_t vol_stride = (int64_t)N * N * N;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t r = r0 + ty + 8 * i;
-    float val = 0.0f;
-    if (v < V && r < rows) {
+    float f[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) f[s] = 0.0f;
+    if (v < VR && r < rows) {
       const int64_t b = r / S;
       const int sh = (int)(r % S);
-      const int si = vi + shifts.d[sh][0], sj = vj + shifts.d[sh][1],
-                sk = vk + shifts.d[sh][2];
-      if (si >= 0 && si < N && sj >= 0 && sj < N && sk >= 0 && sk < N)
-        val = vols[b * vol_stride + ((int64_t)si * N + sj) * N + sk];
+      const float* vb = vols + b * vol_stride;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int si = ((s & 1) ? N - 1 - vi : vi) + shifts.d[sh][0];
+        const int sj = ((s & 2) ? N - 1 - vj : vj) + shifts.d[sh][1];
+        const int sk = ((s & 4) ? N - 1 - vk : vk) + shifts.d[sh][2];
+        if (si >= 0 && si < N && sj >= 0 && sj < N && sk >= 0 && sk < N)
+          f[s] = vb[((int64_t)si * N + sj) * N + sk];
+      }
     }
-    tile[ty + 8 * i][tx] = val;
+    parity_fold(f);
+#pragma unroll
+    for (int c = 0; c < kParityClasses; ++c) tile[c][ty + 8 * i][tx] = f[c];
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t vv = v0 + ty + 8 * i;
-    Ft[vv * M_pad + r0 + tx] = tile[tx][ty + 8 * i];
+  for (int c = 0; c < kParityClasses; ++c) {
+    float* out = Ft + (int64_t)c * VR_pad * M_pad;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t vv = v0 + ty + 8 * i;
+      out[vv * M_pad + r0 + tx] = tile[c][tx][ty + 8 * i];
+    }
   }
 }
 
@@ -107,7 +141,8 @@ __device__ inline void gemm_tile(int64_t bid, int64_t mt, int64_t nt, int64_t ns
 __global__ __launch_bounds__(256, 2) void k_gemm_f32(const float* __restrict__ Ft,
                                                      const float* __restrict__ Psi,
                                                      float* __restrict__ part, int64_t M_pad,
-                                                     int64_t C_pad, int nk, int nsplit) {
+                                                     int64_t C_pad, int64_t VR_pad, ClassTiles ct,
+                                                     int nk, int nsplit) {
   __shared__ float As[2][BK][BM];
   __shared__ float Bs[2][BK][BN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -116,7 +151,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(const float* __restrict__ F
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t k_begin = ts * nk * BK;
   const int lr = tid >> 5, lc = (tid & 31) * 4;
-  const float* pa = Ft + (k_begin + lr) * M_pad + m0 + lc;
+  const float* pa = Ft + class_of_tile(ct, tn) * VR_pad * M_pad + (k_begin + lr) * M_pad + m0 + lc;
   const float* pb = Psi + (k_begin + lr) * C_pad + n0 + lc;
   const int64_t sa = 8 * M_pad, sb = 8 * C_pad;          // 8 rows apart
   const int64_t stepa = BK * M_pad, stepb = BK * C_pad;  // one K step
@@ -211,29 +246,32 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
   if (B == 0) return BH_OK;
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
   const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
-  const int64_t nk_total = p->V_pad / BK;           // multiple of 16
+  const int64_t nk_total = p->VR_pad / BK;          // multiple of 16
   const int nsplit = expand_split(mt, nt, nk_total, batch_invariant, &p->tuned_split[0]);
   const int nk = (int)(nk_total / nsplit);
   int rc;
-  if ((rc = grow(p->gathered, (size_t)p->V_pad * M_pad * sizeof(float))) != BH_OK) return rc;
+  if ((rc = grow(p->gathered, (size_t)kParityClasses * p->VR_pad * M_pad * sizeof(float))) != BH_OK)
+    return rc;
   if ((rc = grow(p->partial, (size_t)nsplit * M_pad * p->C_pad * sizeof(float))) != BH_OK) return rc;
   float* Ft = (float*)p->gathered.ptr;
   float* part = (float*)p->partial.ptr;
   const int64_t vol_stride = (int64_t)p->N * p->N * p->N;
   if (shifts) {
     ProfScope ps(p, "gather_shift", s, B);
-    hipLaunchKernelGGL(k_gather_shift, dim3((unsigned)(p->V_pad / 32), (unsigned)(M_pad / 32)),
-                       dim3(256), 0, s, vols, p->N, B, S, *shifts, p->vidx, p->V, M_pad, Ft);
+    hipLaunchKernelGGL(k_gather_shift, dim3((unsigned)(p->VR_pad / 32), (unsigned)(M_pad / 32)),
+                       dim3(256), 0, s, vols, p->N, B, S, *shifts, p->vrep, p->VR, p->VR_pad,
+                       M_pad, Ft);
   } else {
     ProfScope ps(p, "gather", s, B);
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)(p->V_pad / 32), (unsigned)(M_pad / 32)),
-                       dim3(256), 0, s, vols, vol_stride, B, p->vidx, p->V, M_pad, Ft);
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)(p->VR_pad / 32), (unsigned)(M_pad / 32)),
+                       dim3(256), 0, s, vols, vol_stride, B, p->vrep, p->VR, p->VR_pad, M_pad,
+                       p->N, Ft);
   }
   BH_HIP(hipGetLastError());
   {
   ProfScope ps(p, "gemm", s, B);
   hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)(mt * nt * nsplit)), dim3(256), 0, s, Ft, p->psi,
-                     part, M_pad, p->C_pad, nk, nsplit);
+                     part, M_pad, p->C_pad, p->VR_pad, p->ctiles, nk, nsplit);
   }
   BH_HIP(hipGetLastError());
   const int64_t tot = B * p->C;
@@ -249,15 +287,14 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
 int tune_expand_f32(bh_plan* p, int64_t B, hipStream_t s) {
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
   const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
-  const int64_t nk_total = p->V_pad / BK;
+  const int64_t nk_total = p->VR_pad / BK;
+  const size_t fbytes = (size_t)kParityClasses * p->VR_pad * M_pad * sizeof(float);
   int rc;
-  if ((rc = grow(p->gathered, (size_t)p->V_pad * M_pad * sizeof(float))) != BH_OK) return rc;
+  if ((rc = grow(p->gathered, fbytes)) != BH_OK) return rc;
   if ((rc = grow(p->partial, (size_t)16 * M_pad * p->C_pad * sizeof(float))) != BH_OK) return rc;
   float* Ft = (float*)p->gathered.ptr;
   float* part = (float*)p->partial.ptr;
-  // timing data: the basis itself stands in for the volumes (any finite values)
-  BH_HIP(hipMemcpyAsync(Ft, p->psi, (size_t)p->V_pad * std::min(M_pad, p->C_pad) * sizeof(float),
-                        hipMemcpyDeviceToDevice, s));
+  BH_HIP(hipMemsetAsync(Ft, 0, fbytes, s));   // timing data: any finite values
   float best_ms = 1e30f;
   int best = 1;
   for (int ns = 1; ns <= 16; ns *= 2) {
@@ -267,7 +304,8 @@ int tune_expand_f32(bh_plan* p, int64_t B, hipStream_t s) {
         s, 2, [] {},
         [&] {
           hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)(mt * nt * ns)), dim3(256), 0, s, Ft,
-                             p->psi, part, M_pad, p->C_pad, (int)(nk_total / ns), ns);
+                             p->psi, part, M_pad, p->C_pad, p->VR_pad, p->ctiles,
+                             (int)(nk_total / ns), ns);
         },
         &ms);
     if (rc != BH_OK) return rc;

@@ -8,9 +8,12 @@
 // Both are computed by one kernel with two accumulator sets; the three
 // products use v_mfma_f32_32x32x16_bf16.
 //
-//   k_psi_split : Psi[V_pad][C_pad] FP32 -> Ph, Pl [C_pad][V_pad] BF16 (once per plan)
-//   k_gather_split: vols -> Fh, Fl [M_pad][V_pad] BF16 (ball voxels, zero padded)
-//   k_gemm_bf16 : split-K partial sums, 128x128 tiles, K step 32 voxels
+//   k_psi_split : Psi[VR_pad][C_pad] FP32 -> Ph, Pl [C_pad][VR_pad] BF16 (once per plan)
+//   k_gather_split: vols -> Fh, Fl [8][M_pad][VR_pad] BF16: the mirror sums
+//                 of each parity class at the orbit representatives (as the
+//                 FP32 path), zero padded
+//   k_gemm_bf16 : split-K partial sums, 128x128 tiles, K step 32 voxels; a
+//                 column tile reads the slice of its class
 //   k_reduce2   : sums splits, scatters to the complex layout
 //
 // Operands are K-contiguous rows (particles, coefficients), staged in LDS
@@ -39,7 +42,7 @@ __device__ inline uint16_t bf16_bits(float x) {
 __device__ inline float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // Ph[c][v], Pl[c][v] from Psi[v][c]: 32x32 LDS transpose and split.
-__global__ __launch_bounds__(256) void k_psi_split(const float* __restrict__ psi, int64_t V_pad,
+__global__ __launch_bounds__(256) void k_psi_split(const float* __restrict__ psi, int64_t VR_pad,
                                                    int64_t C_pad, uint16_t* __restrict__ ph,
                                                    uint16_t* __restrict__ pl) {
   __shared__ float tile[32][33];
@@ -52,27 +55,38 @@ __global__ __launch_bounds__(256) void k_psi_split(const float* __restrict__ psi
   for (int i = 0; i < 4; ++i) {
     const float x = tile[tx][ty + 8 * i];
     const uint16_t h = bf16_bits(x);
-    const int64_t o = (c0 + ty + 8 * i) * V_pad + v0 + tx;
+    const int64_t o = (c0 + ty + 8 * i) * VR_pad + v0 + tx;
     ph[o] = h;
     pl[o] = bf16_bits(x - bf16_value(h));
   }
 }
 
-// Fh[b][v], Fl[b][v] = split of vols[b][vidx[v]] (0 outside v < V, b < B).
+// Fh[P][b][v], Fl[P][b][v] = split of the class-P mirror sum of particle b
+// at representative v (0 outside v < VR, b < B).
 __global__ __launch_bounds__(256) void k_gather_split(const float* __restrict__ vols,
                                                       int64_t vol_stride, int64_t B,
-                                                      const int32_t* __restrict__ vidx, int64_t V,
-                                                      int64_t V_pad, int64_t M_pad,
+                                                      const int32_t* __restrict__ vrep, int64_t VR,
+                                                      int64_t VR_pad, int64_t M_pad, int N,
                                                       uint16_t* __restrict__ fh,
                                                       uint16_t* __restrict__ fl) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (v >= V_pad) return;
-  const int32_t lin = (v < V) ? vidx[v] : 0;
+  if (v >= VR_pad) return;
+  int32_t off[8];
+  mirror_offsets((v < VR) ? vrep[v] : 0, N, off);
+  const int64_t slab = M_pad * VR_pad;
   for (int64_t b = blockIdx.y; b < M_pad; b += gridDim.y) {
-    const float x = (v < V && b < B) ? vols[b * vol_stride + lin] : 0.0f;
-    const uint16_t h = bf16_bits(x);
-    fh[b * V_pad + v] = h;
-    fl[b * V_pad + v] = bf16_bits(x - bf16_value(h));
+    float f[8];
+    const bool in = v < VR && b < B;
+    const float* vb = vols + (in ? b * vol_stride : 0);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) f[s] = in ? vb[off[s]] : 0.0f;
+    parity_fold(f);
+#pragma unroll
+    for (int c = 0; c < kParityClasses; ++c) {
+      const uint16_t h = bf16_bits(f[c]);
+      fh[c * slab + b * VR_pad + v] = h;
+      fl[c * slab + b * VR_pad + v] = bf16_bits(f[c] - bf16_value(h));
+    }
   }
 }
 
@@ -101,8 +115,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict
                                                       const uint16_t* __restrict__ pl,
                                                       float* __restrict__ part_c,
                                                       float* __restrict__ part_r, int64_t M_pad,
-                                                      int64_t C_pad, int64_t V_pad, int nk,
-                                                      int nsplit) {
+                                                      int64_t C_pad, int64_t VR_pad, ClassTiles ct,
+                                                      int nk, int nsplit) {
   constexpr bool LO = CORR;
   __shared__ __attribute__((aligned(16))) uint16_t Ah[2][BM][ROW];
   __shared__ __attribute__((aligned(16))) uint16_t Bh[2][BN][ROW];
@@ -115,11 +129,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict
   const int64_t k_begin = ts * (int64_t)nk * BK;
   // global -> LDS: 128 rows x 32 voxels = 512 chunks of 8 BF16; two per thread
   const int r0 = tid >> 2, r1 = r0 + 64, cc = (tid & 3) * 8;
-  const uint16_t* ga_h = fh + (m0 + r0) * V_pad + k_begin + cc;
-  const uint16_t* gb_h = ph + (n0 + r0) * V_pad + k_begin + cc;
-  const uint16_t* ga_l = LO ? fl + (m0 + r0) * V_pad + k_begin + cc : nullptr;
-  const uint16_t* gb_l = LO ? pl + (n0 + r0) * V_pad + k_begin + cc : nullptr;
-  const int64_t off64a = 64 * V_pad, off64b = 64 * V_pad;
+  const int64_t slab = class_of_tile(ct, tn) * M_pad * VR_pad;
+  const uint16_t* ga_h = fh + slab + (m0 + r0) * VR_pad + k_begin + cc;
+  const uint16_t* gb_h = ph + (n0 + r0) * VR_pad + k_begin + cc;
+  const uint16_t* ga_l = LO ? fl + slab + (m0 + r0) * VR_pad + k_begin + cc : nullptr;
+  const uint16_t* gb_l = LO ? pl + (n0 + r0) * VR_pad + k_begin + cc : nullptr;
+  const int64_t off64a = 64 * VR_pad, off64b = 64 * VR_pad;
   uint4 xah0, xah1, xbh0, xbh1, xal0, xal1, xbl0, xbl1;
 #define BH_LOAD(kt)                                                                   \
   do {                                                                                \
@@ -248,7 +263,7 @@ __global__ __launch_bounds__(256) void k_reduce2(const float* __restrict__ part_
 
 int ensure_bf16_basis(bh_plan* p) {
   if (p->psi_h) return BH_OK;
-  const size_t n = (size_t)p->C_pad * p->V_pad;
+  const size_t n = (size_t)p->C_pad * p->VR_pad;
   if (hipMalloc((void**)&p->psi_h, n * sizeof(uint16_t)) != hipSuccess ||
       hipMalloc((void**)&p->psi_l, n * sizeof(uint16_t)) != hipSuccess) {
     if (p->psi_h) (void)hipFree(p->psi_h);
@@ -257,8 +272,8 @@ int ensure_bf16_basis(bh_plan* p) {
     (void)hipGetLastError();
     return set_error(BH_ENOMEM, "BF16 basis allocation failed");
   }
-  hipLaunchKernelGGL(k_psi_split, dim3((unsigned)(p->V_pad / 32), (unsigned)(p->C_pad / 32)),
-                     dim3(256), 0, 0, p->psi, p->V_pad, p->C_pad, p->psi_h, p->psi_l);
+  hipLaunchKernelGGL(k_psi_split, dim3((unsigned)(p->VR_pad / 32), (unsigned)(p->C_pad / 32)),
+                     dim3(256), 0, 0, p->psi, p->VR_pad, p->C_pad, p->psi_h, p->psi_l);
   BH_HIP(hipGetLastError());
   BH_HIP(hipDeviceSynchronize());
   return BH_OK;
@@ -272,23 +287,23 @@ int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, fl
   if (rc != BH_OK) return rc;
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
   const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
-  const int64_t nk_total = p->V_pad / BK;   // multiple of 16
+  const int64_t nk_total = p->VR_pad / BK;   // multiple of 16
   const int nsplit = expand_split(mt, nt, nk_total, batch_invariant, &p->tuned_split[1]);
   const int nk = (int)(nk_total / nsplit);
-  const size_t fbytes = (size_t)M_pad * p->V_pad * sizeof(uint16_t);
+  const size_t fbytes = (size_t)kParityClasses * M_pad * p->VR_pad * sizeof(uint16_t);
   const size_t pbytes = (size_t)nsplit * M_pad * p->C_pad * sizeof(float);
   if ((rc = grow(p->gathered, 2 * fbytes)) != BH_OK) return rc;
   if ((rc = grow(p->partial, (refine ? 2 : 1) * pbytes)) != BH_OK) return rc;
   uint16_t* fh = (uint16_t*)p->gathered.ptr;
-  uint16_t* fl = fh + (size_t)M_pad * p->V_pad;
+  uint16_t* fl = fh + fbytes / sizeof(uint16_t);
   float* part_c = (float*)p->partial.ptr;
   float* part_r = refine ? part_c + (size_t)nsplit * M_pad * p->C_pad : nullptr;
   const int64_t vol_stride = (int64_t)p->N * p->N * p->N;
   {
     ProfScope ps(p, "gather_bf16", s, B);
     const unsigned gy = (unsigned)(M_pad < 4096 ? M_pad : 4096);
-    hipLaunchKernelGGL(k_gather_split, dim3((unsigned)((p->V_pad + 255) / 256), gy), dim3(256), 0,
-                       s, vols, vol_stride, B, p->vidx, p->V, p->V_pad, M_pad, fh, fl);
+    hipLaunchKernelGGL(k_gather_split, dim3((unsigned)((p->VR_pad + 255) / 256), gy), dim3(256),
+                       0, s, vols, vol_stride, B, p->vrep, p->VR, p->VR_pad, M_pad, p->N, fh, fl);
   }
   BH_HIP(hipGetLastError());
   {
@@ -296,10 +311,12 @@ int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, fl
     const dim3 grid((unsigned)(mt * nt * nsplit));
     if (refine)
       hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, dim3(256), 0, s, fh, fl, p->psi_h,
-                         p->psi_l, part_c, part_r, M_pad, p->C_pad, p->V_pad, nk, nsplit);
+                         p->psi_l, part_c, part_r, M_pad, p->C_pad, p->VR_pad, p->ctiles, nk,
+                         nsplit);
     else
       hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, dim3(256), 0, s, fh, fl, p->psi_h,
-                         p->psi_l, part_c, part_c, M_pad, p->C_pad, p->V_pad, nk, nsplit);
+                         p->psi_l, part_c, part_c, M_pad, p->C_pad, p->VR_pad, p->ctiles, nk,
+                         nsplit);
   }
   BH_HIP(hipGetLastError());
   {
@@ -318,18 +335,15 @@ int tune_expand_bf16(bh_plan* p, int64_t B, hipStream_t s) {
   if (rc != BH_OK) return rc;
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
   const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
-  const int64_t nk_total = p->V_pad / BK;
-  const size_t fbytes = (size_t)M_pad * p->V_pad * sizeof(uint16_t);
+  const int64_t nk_total = p->VR_pad / BK;
+  const size_t fbytes = (size_t)kParityClasses * M_pad * p->VR_pad * sizeof(uint16_t);
   if ((rc = grow(p->gathered, 2 * fbytes)) != BH_OK) return rc;
   if ((rc = grow(p->partial, (size_t)2 * 16 * M_pad * p->C_pad * sizeof(float))) != BH_OK)
     return rc;
   uint16_t* fh = (uint16_t*)p->gathered.ptr;
-  uint16_t* fl = fh + (size_t)M_pad * p->V_pad;
+  uint16_t* fl = fh + fbytes / sizeof(uint16_t);
   float* part = (float*)p->partial.ptr;
-  // timing data: BF16 basis values stand in for the volumes (any finite values)
-  const size_t n = (size_t)std::min(M_pad, p->C_pad) * p->V_pad * sizeof(uint16_t);
-  BH_HIP(hipMemcpyAsync(fh, p->psi_h, n, hipMemcpyDeviceToDevice, s));
-  BH_HIP(hipMemcpyAsync(fl, p->psi_l, n, hipMemcpyDeviceToDevice, s));
+  BH_HIP(hipMemsetAsync(fh, 0, 2 * fbytes, s));   // timing data: any finite values
   float best_ms = 1e30f;
   int best = 1;
   for (int ns = 1; ns <= 16; ns *= 2) {
@@ -340,8 +354,8 @@ int tune_expand_bf16(bh_plan* p, int64_t B, hipStream_t s) {
         [&] {
           hipLaunchKernelGGL((k_gemm_bf16<true, true>), dim3((unsigned)(mt * nt * ns)), dim3(256),
                              0, s, fh, fl, p->psi_h, p->psi_l, part,
-                             part + (size_t)ns * M_pad * p->C_pad, M_pad, p->C_pad, p->V_pad,
-                             (int)(nk_total / ns), ns);
+                             part + (size_t)ns * M_pad * p->C_pad, M_pad, p->C_pad, p->VR_pad,
+                             p->ctiles, (int)(nk_total / ns), ns);
         },
         &ms);
     if (rc != BH_OK) return rc;

@@ -27,10 +27,56 @@ int set_error(int code, const std::string& msg);
 
 // -------------------------------------------------------------- GEMM shape --
 // Expansion GEMM a[b][c] = sum_v F[b][v] Psi[v][c] on MFMA f32 32x32x2.
+//
+// The cell-centred ball is symmetric under the reflections x, y, z -> -x,
+// -y, -z, and every real basis column is even or odd under each of them
+// (its parity class P, 3 bits).  With g_P(v) = sum over the 8 reflections R
+// of chi_P(R) f(R v) at one representative v per orbit (chi_P(R) = -1 when
+// R flips an odd number of the axes P marks), the column's coefficient is
+// sum_v g_P(v) Psi(v) / |orbit stabiliser| over the representatives only:
+// the GEMM runs over an eighth of the voxels, class by class.  Columns are
+// stored class after class, each class padded to whole column tiles.
 constexpr int kGemmBM = 128;     // particles per tile
 constexpr int kGemmBN = 128;     // coefficients per tile
 constexpr int kGemmBK = 32;      // voxels per K step
-constexpr int kGemmKAlign = kGemmBK * 16;   // V padded to this, split-K <= 16
+constexpr int kGemmKAlign = kGemmBK * 16;   // VR padded to this, split-K <= 16
+constexpr int kParityClasses = 8;
+
+// Column tiles [first[P], first[P+1]) hold parity class P; passed by value.
+struct ClassTiles {
+  int32_t first[kParityClasses + 1];
+};
+__host__ __device__ inline int class_of_tile(const ClassTiles& ct, int64_t tn) {
+  int c = 0;
+  while (c < kParityClasses - 1 && tn >= ct.first[c + 1]) ++c;
+  return c;
+}
+
+// The 8 mirror images of voxel (i, j, k): image s (bit 0: i -> N-1-i,
+// bit 1: j, bit 2: k) at linear offset off[s].
+__device__ inline void mirror_offsets(int32_t lin, int N, int32_t off[8]) {
+  const int i = lin / (N * N), j = (lin / N) % N, k = lin % N;
+  const int32_t I[2] = {i * N * N, (N - 1 - i) * N * N};
+  const int32_t J[2] = {j * N, (N - 1 - j) * N};
+  const int32_t K[2] = {k, N - 1 - k};
+#pragma unroll
+  for (int s = 0; s < 8; ++s) off[s] = I[s & 1] + J[(s >> 1) & 1] + K[s >> 2];
+}
+
+// In place: f[P] = sum_s (-1)^popcount(P & s) f[s] (size-8 Walsh-Hadamard),
+// the mirror sum g_P of parity class P from the 8 image values.
+__device__ inline void parity_fold(float f[8]) {
+#pragma unroll
+  for (int h = 1; h < 8; h <<= 1) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      if (s & h) continue;
+      const float a = f[s], b = f[s | h];
+      f[s] = a + b;
+      f[s | h] = a - b;
+    }
+  }
+}
 
 // The score loop loads table entries ahead of use; tables and per-particle
 // cross-power buffers carry this many zero entries past their end.
@@ -80,12 +126,14 @@ struct Profiler {
 struct bh_plan {
   int N = 0, L_max = 0, device = 0;
   const bh::IndexSet* idx = nullptr;
-  int64_t V = 0, V_pad = 0;      // ball voxels, padded to kGemmKAlign
-  int64_t C = 0, C_pad = 0;      // complex coefficients of L_max, padded to kGemmBN
-  float* psi = nullptr;          // [V_pad][C_pad] h^3 * real columns of conj(psi)
-  uint16_t* psi_h = nullptr;     // [C_pad][V_pad] BF16 of psi (built on first BF16 use)
-  uint16_t* psi_l = nullptr;     // [C_pad][V_pad] BF16 of psi - psi_h
-  int32_t* vidx = nullptr;       // [V] linear voxel index of each ball voxel
+  int64_t V = 0;                 // ball voxels
+  int64_t VR = 0, VR_pad = 0;    // orbit representatives, padded to kGemmKAlign
+  int64_t C = 0, C_pad = 0;      // complex coefficients of L_max; real columns with class padding
+  bh::ClassTiles ctiles = {};    // column tiles of each parity class
+  float* psi = nullptr;          // [VR_pad][C_pad] h^3 / |stabiliser| * real columns of conj(psi)
+  uint16_t* psi_h = nullptr;     // [C_pad][VR_pad] BF16 of psi (built on first BF16 use)
+  uint16_t* psi_l = nullptr;     // [C_pad][VR_pad] BF16 of psi - psi_h
+  int32_t* vrep = nullptr;       // [VR] linear voxel index of each orbit representative
   int32_t* csrc = nullptr;       // [C][2] real column feeding re/im of each complex coefficient
   float* csgn = nullptr;         // [C][2] sign applied to it
   std::vector<int64_t> band_size;   // C(L) for L = 0..L_max

@@ -119,6 +119,34 @@ std::vector<int32_t> ball_voxels(int N) {
   return v;
 }
 
+std::vector<int32_t> orbit_representatives(int N) {
+  std::vector<int32_t> v;
+  const long long N2 = (long long)N * N;
+  for (int i = N / 2; i < N; ++i) {
+    const long long a = 2LL * i - (N - 1);
+    for (int j = N / 2; j < N; ++j) {
+      const long long b = 2LL * j - (N - 1);
+      for (int k = N / 2; k < N; ++k) {
+        const long long c = 2LL * k - (N - 1);
+        if (a * a + b * b + c * c < N2) v.push_back((int32_t)(((long long)i * N + j) * N + k));
+      }
+    }
+  }
+  return v;
+}
+
+// x -> -x maps phi to pi - phi: cos m phi keeps the sign (-1)^m, sin m phi
+// takes (-1)^(m+1); y -> -y maps phi to -phi (sin odd); z -> -z maps
+// cos theta to -cos theta, and P_l^m(-t) = (-1)^(l+m) P_l^m(t).
+int column_parity_class(int l, int j) {
+  const int m = (j + 1) / 2;
+  const bool sine = j > 0 && (j % 2 == 0);
+  const int cx = sine ? (m + 1) & 1 : m & 1;
+  const int cy = sine ? 1 : 0;
+  const int cz = (l + m) & 1;
+  return cx | (cy << 1) | (cz << 2);
+}
+
 int64_t wave_block_offset(int L, int W) {
   int64_t off = 0;
   for (int wi = 0; wi < kNumWaveChoices; ++wi) {

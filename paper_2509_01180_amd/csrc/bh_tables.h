@@ -33,6 +33,16 @@ const IndexSet& index_set(int L);
 // Number of ball voxels of the N^3 cell-centred grid and their linear indices.
 std::vector<int32_t> ball_voxels(int N);
 
+// Ball voxels with all three coordinates >= 0: one voxel of each orbit of
+// the three coordinate-plane reflections (linear indices, k fastest).  On
+// an odd grid an orbit touching a mirror plane has fewer than 8 members.
+std::vector<int32_t> orbit_representatives(int N);
+
+// Parity class 0..7 of real basis column j (0: m = 0; 2m-1: cos m phi;
+// 2m: sin m phi) of degree l under the reflections x -> -x (bit 0),
+// y -> -y (bit 1), z -> -z (bit 2): a set bit means the column changes sign.
+int column_parity_class(int l, int j);
+
 // ---------------------------------------------------------------------------
 // Score tables of one band L.
 //
