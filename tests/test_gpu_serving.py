@@ -182,6 +182,47 @@ def test_served_result_matches_oracle():
     plan.close()
 
 
+def test_paper_method_served_matches_oracle():
+    """One 24^3 particle served with the paper procedure in a mix (bands
+    4-7-10: gradient steps on band 4, 6 candidates 10 degrees apart, Newton
+    steps on bands 7 and 10); oracle: the same procedure on FP64
+    coefficients from the same starts."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd.serving import Engine, Request
+    dev = cuda_device()
+    N, L, bands = 24, 10, (4, 7, 10)
+    keep, nsteps, sep = 6, 4, np.radians(10.0)
+    plan = Plan(N, L, device=0)
+    tmpl, blobs = _templates(plan, N)
+    v, g = _particles(blobs, N, 1, 3, 91)
+    st = synth.serving.start_pool(3, P, seed=91)
+    say(f"served (paper procedure) vs oracle N={N} L={L}")
+    eng = Engine({N: (L, bands)}, {N: tmpl}, restarts=P, steps=STEPS, plans={N: plan},
+                 method="paper", keep=keep, min_sep=sep, newton_steps=nsteps)
+    other = eng.submit(Request(box=N, template=0, n=4,
+                               volumes=torch.from_numpy(_particles(blobs, N, 0, 4, 92)[0]).to(dev),
+                               starts=torch.from_numpy(synth.serving.start_pool(4, P, 92)).to(dev)))
+    r = eng.submit(Request(box=N, template=1, n=3, volumes=torch.from_numpy(v).to(dev),
+                           starts=torch.from_numpy(st).to(dev)))
+    eng.drain()
+    assert other.done is not None
+    idx = basis.IndexSet(L)
+    b = expand.expand(synth.render_blobs(blobs[1], N)[None].astype(np.float32).astype(np.float64), idx)[0]
+    A = expand.expand(v.astype(np.float64), idx)
+    for i in range(3):
+        o = oalign.march(A[i], b, idx, bands, st[i], STEPS, newton_bands=len(bands) - 1,
+                         newton_steps=nsteps, keep=keep, min_sep=sep)
+        e_ref, s_ref = o["euler"][o["best"]], o["score"][o["best"]]
+        ang = wigner.geodesic_deg(wigner.euler_to_matrix(*r.euler[i]), wigner.euler_to_matrix(*e_ref))
+        print(f"particle {i}: served vs oracle {ang:.3f} deg, score {r.score[i]:.8g} vs {s_ref:.8g}")
+        assert ang <= 1.0 or abs(r.score[i] - s_ref) <= 1e-4 * abs(s_ref)
+        assert abs(r.score[i] - s_ref) <= 1e-3 * abs(s_ref)
+        # and the planted rotation is found (SNR 1)
+        assert wigner.geodesic_deg(wigner.euler_to_matrix(*r.euler[i]), g[i].T) < 3.0
+    plan.close()
+
+
 def test_paper_method_same_alone_and_in_mix():
     """The paper procedure in the serving loop (candidates after the lowest
     band, Newton steps on the higher ones): each request's result is the
