@@ -253,7 +253,7 @@ void bh_plan_destroy(bh_plan* p) {
                   (void*)p->csgn})
     if (q) (void)hipFree(q);
   for (Buffer* b : {&p->gathered, &p->partial, &p->xi_scr, &p->state_scr, &p->misc_scr,
-                    &p->prune_scr, &p->shift_scr})
+                    &p->prune_scr, &p->shift_scr, &p->newton_scr})
     if (b->ptr) (void)hipFree(b->ptr);
   for (auto& kv : p->bands) free_band(kv.second);
   p->prof.destroy();

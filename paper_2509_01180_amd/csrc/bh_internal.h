@@ -138,7 +138,7 @@ struct bh_plan {
   float* csgn = nullptr;         // [C][2] sign applied to it
   std::vector<int64_t> band_size;   // C(L) for L = 0..L_max
   // scratch (grown on demand, owned by the plan)
-  bh::Buffer gathered, partial, xi_scr, state_scr, misc_scr, prune_scr, shift_scr;
+  bh::Buffer gathered, partial, xi_scr, state_scr, misc_scr, prune_scr, shift_scr, newton_scr;
   std::map<int, bh::DevBand> bands;
   bh::Profiler prof;
   // autotuned launch shapes (0 / absent: the built-in rules)

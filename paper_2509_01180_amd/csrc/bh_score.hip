@@ -420,6 +420,123 @@ __global__ __launch_bounds__(64 * W) BH_MARCH_OCCUPANCY(NEWTON, G < 64) void k_m
   }
 }
 
+// Newton bands of packed restarts (at most 32 per particle), one launch per
+// evaluation: the classes of each group of 64 / G particles are split over
+// kNewtonParts workgroups of kNewtonWaves waves (the work split of
+// kNewtonParts * kNewtonWaves waves), so a group occupies several CUs; a
+// step kernel adds the parts in a fixed order and makes the Newton update.
+// The per-lane rule is the ascent kernel's (NEWTON).
+constexpr int kNewtonParts = 4, kNewtonWaves = 4;
+static_assert(kNewtonParts * kNewtonWaves == 16, "the work split of 16 waves is used");
+
+// trial[b][r] = the wrapped carried rotation (the first evaluation point).
+template <int G>
+__global__ __launch_bounds__(64) void k_newton_init(const double* __restrict__ state, int64_t B,
+                                                    int P, double* __restrict__ trial) {
+  constexpr int PER = 64 / G;
+  const int lane = threadIdx.x;
+  const int64_t pb = (int64_t)blockIdx.x * PER + lane / G;
+  const int r = lane % G;
+  if (pb >= B || r >= P) return;
+  const int64_t i = pb * P + r;
+  double a = state[i * 3], b = state[i * 3 + 1], g = state[i * 3 + 2];
+  wrap_euler(a, b, g);
+  trial[i * 3] = a;
+  trial[i * 3 + 1] = b;
+  trial[i * 3 + 2] = g;
+}
+
+// part[group][sp][k][lane]: score, gradient and Hessian sums of part sp of
+// the classes at the trial rotations.
+template <int G>
+__global__ __launch_bounds__(64 * kNewtonWaves) BH_HESS_OCCUPANCY(true) void k_newton_part(
+    const int32_t* __restrict__ p_first, const int32_t* __restrict__ wave_p,
+    const double* __restrict__ rec, const double* __restrict__ X, int64_t n_entries, int L,
+    int64_t B, int P, const double* __restrict__ trial, double* __restrict__ part) {
+  constexpr int W = kNewtonWaves, NV = 10, PER = 64 / G;
+  __shared__ double red[W * NV * 64];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int sp = blockIdx.x;
+  const int64_t grp = blockIdx.y;
+  int64_t pb = grp * PER + lane / G;
+  const int r = lane % G;
+  const bool active = pb < B && r < P;
+  if (pb >= B) pb = B - 1;          // idle lanes read a valid particle
+  double al = 0.0, be = 0.0, ga = 0.0;
+  if (active) {
+    const double* t = trial + (pb * P + r) * 3;
+    al = t[0];
+    be = t[1];
+    ga = t[2];
+  }
+  const Angles A = prep(al, be, ga);
+  const Acc mine = eval_wave<true>(A, wave_p + (sp * W + wave) * (2 * L + 2), L, p_first, rec,
+                                   X + pb * n_entries * 4);
+  store_partials<NV>(mine, red, wave, lane);
+  __syncthreads();
+  if (wave == 0) {
+    const Acc t = sum_partials<NV>(red, lane, W);
+    const double v[NV] = {t.S, t.ga, t.gb, t.gg, t.haa, t.hab, t.hag, t.hbb, t.hbg, t.hgg};
+    double* o = part + (grp * kNewtonParts + sp) * NV * 64 + lane;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) o[k * 64] = v[k];
+  }
+}
+
+// Evaluation t of a Newton band (t = 0: the carried point): accept the trial
+// point if not worse (t = 0: always), adapt the damping mu <= 1, and (t <
+// steps) place the next trial point.  nst[b][r] = (gradient, Hessian, mu).
+template <int G>
+__global__ __launch_bounds__(64) void k_newton_step(
+    const double* __restrict__ part, const double* __restrict__ Wb, int64_t B, int P, int t,
+    int steps, double step_init, double grow, double shrink, double* __restrict__ state,
+    double* __restrict__ sscore, double* __restrict__ trial, double* __restrict__ nst) {
+  constexpr int NV = 10, PER = 64 / G;
+  const int lane = threadIdx.x;
+  const int64_t grp = blockIdx.x;
+  const int64_t pb = grp * PER + lane / G;
+  const int r = lane % G;
+  if (pb >= B || r >= P) return;
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double acc = 0.0;
+    for (int sp = 0; sp < kNewtonParts; ++sp)
+      acc += part[((grp * kNewtonParts + sp) * NV + k) * 64 + lane];
+    v[k] = acc;
+  }
+  const int64_t i = pb * P + r;
+  double* x = state + i * 3;
+  double* tr = trial + i * 3;
+  double* ns = nst + i * 10;
+  double eta = (t == 0) ? 1.0 : ns[9];
+  const bool take = (t == 0) || (v[0] >= sscore[i]);
+  if (take) {
+    x[0] = tr[0];
+    x[1] = tr[1];
+    x[2] = tr[2];
+    sscore[i] = v[0];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) ns[k] = v[k + 1];
+  }
+  if (t > 0) eta = take ? fmin(1.0, eta * grow) : eta * shrink;
+  ns[9] = eta;
+  if (t < steps) {
+    const double wb = Wb[pb];
+    const double eta0 = (wb > 0.0) ? step_init / wb : 0.0;
+    double da, db, dg;
+    newton_direction(x[1], ns[0], ns[1], ns[2], ns + 3, eta0, da, db, dg);
+    double ta = x[0] + eta * da;
+    double tb = x[1] + eta * db;
+    double tg = x[2] + eta * dg;
+    wrap_euler(ta, tb, tg);
+    tr[0] = ta;
+    tr[1] = tb;
+    tr[2] = tg;
+  }
+}
+
 // Best restart per particle (highest score, lowest index on ties).
 __global__ __launch_bounds__(64) void k_select(const double* __restrict__ state,
                                                const double* __restrict__ sscore, int P,
@@ -719,6 +836,42 @@ void launch_march_any(int W, int G, bh_plan* p, int64_t B, hipStream_t s, const 
   }
 }
 
+template <int G>
+int launch_newton_split_g(bh_plan* p, int64_t B, hipStream_t s, const DevBand& band,
+                          const double* X, const double* Wb, int P, int steps,
+                          const bh_align_opts& o, double* state, double* sscore) {
+  constexpr int PER = 64 / G;
+  const int64_t groups = (B + PER - 1) / PER;
+  const size_t n_lane = (size_t)B * P;
+  const size_t n_part = (size_t)groups * kNewtonParts * 10 * 64;
+  int rc = grow(p->newton_scr, (n_lane * 13 + n_part) * sizeof(double));
+  if (rc != BH_OK) return rc;
+  double* trial = (double*)p->newton_scr.ptr;
+  double* nst = trial + n_lane * 3;
+  double* part = nst + n_lane * 10;
+  const int L = band.L;
+  ProfScope ps(p, "newton_L" + std::to_string(L), s, groups * PER * P * band.n_entries);
+  const int32_t* wp = band.wave_p + wave_block_offset(L, kNewtonParts * kNewtonWaves);
+  hipLaunchKernelGGL(k_newton_init<G>, dim3((unsigned)groups), dim3(64), 0, s, state, B, P, trial);
+  for (int t = 0; t <= steps; ++t) {
+    hipLaunchKernelGGL(k_newton_part<G>, dim3(kNewtonParts, (unsigned)groups),
+                       dim3(64 * kNewtonWaves), 0, s, band.p_first, wp, band.rec, X,
+                       band.n_entries, L, B, P, trial, part);
+    hipLaunchKernelGGL(k_newton_step<G>, dim3((unsigned)groups), dim3(64), 0, s, part, Wb, B, P, t,
+                       steps, o.step_init, o.step_grow, o.step_shrink, state, sscore, trial, nst);
+  }
+  BH_HIP(hipGetLastError());
+  return BH_OK;
+}
+
+int launch_newton_split(int G, bh_plan* p, int64_t B, hipStream_t s, const DevBand& band,
+                        const double* X, const double* Wb, int P, int steps,
+                        const bh_align_opts& o, double* state, double* sscore) {
+  if (G == 8) return launch_newton_split_g<8>(p, B, s, band, X, Wb, P, steps, o, state, sscore);
+  if (G == 16) return launch_newton_split_g<16>(p, B, s, band, X, Wb, P, steps, o, state, sscore);
+  return launch_newton_split_g<32>(p, B, s, band, X, Wb, P, steps, o, state, sscore);
+}
+
 int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b,
                  const int32_t* tmpl, int n_tmpl, int64_t B, double** X, hipStream_t s,
                  int64_t lda = 0, int64_t ldt = 0) {
@@ -821,7 +974,13 @@ int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl
     const bool newton = bi >= o.n_bands - o.newton_bands;
     if (newton) {
       const int steps = o.newton_steps > 0 ? o.newton_steps : o.steps_per_band;
-      launch_march_any<true>(W, G, p, B, s, *band, X, Wb, P, steps, o, state, sscore);
+      if (G < 64) {
+        if ((rc = launch_newton_split(G, p, B, s, *band, X, Wb, P, steps, o, state, sscore)) !=
+            BH_OK)
+          return rc;
+      } else {
+        launch_march_any<true>(W, G, p, B, s, *band, X, Wb, P, steps, o, state, sscore);
+      }
     } else {
       launch_march_any<false>(W, G, p, B, s, *band, X, Wb, P, o.steps_per_band, o, state,
                               sscore);

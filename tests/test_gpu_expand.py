@@ -58,12 +58,41 @@ def test_expand_ragged_tiles():
 
 
 def test_expand_odd_box_and_low_bandlimit():
-    for N, L in [(17, 6), (9, 0)]:
+    """Odd boxes put voxels on the three mirror planes (orbits of fewer than
+    8 voxels in the folded sum); both the FP32 and the split-BF16 paths."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    for N, L in [(17, 6), (9, 0), (15, 9)]:
         rng = np.random.default_rng(N)
         vols = rng.standard_normal((5, N, N, N)).astype(np.float32)
         ref = expand.expand(vols.astype(np.float64), basis.IndexSet(L))
         got = run_gpu(N, L, vols)
         assert np.all(normwise(got, ref) <= TOL)
+        plan = Plan(N, L, device=0)
+        c3 = plan.expand_ex(torch.from_numpy(vols).to(cuda_device()), "bf16x3")
+        torch.cuda.synchronize()
+        plan.close()
+        # Random volumes cancel heavily, so the split-BF16 bar is per
+        # coefficient against sum_v |f psi| (see split_bf16_scale).
+        d = to_complex(c3) - ref
+        sr, si = split_bf16_scale(vols, L)
+        assert np.all(np.abs(d.real) <= 2.0 ** -14 * sr)
+        assert np.all(np.abs(d.imag) <= 2.0 ** -14 * si)
+
+
+def split_bf16_scale(vols, L):
+    """sum_v |f(v)| |Re h^3 psi(v)| and the same with Im, per coefficient.
+
+    Split-BF16 (x = hi + lo + r, |lo| <= 2^-9 |x|, |r| <= 2^-18 |x|) keeps
+    hi*hi + hi*lo + lo*hi of each product: the dropped parts are at most
+    3 * 2^-18 |x y|; FP32 accumulation of K terms adds at most K * 2^-24 of
+    the same sum (K <= 500 here).  Both stay below 2^-14 times this scale."""
+    N = vols.shape[-1]
+    idx = basis.IndexSet(L)
+    h, xyz, ball = basis.grid(N)
+    P = basis.psi(idx, xyz[ball]) * h ** 3
+    F = np.abs(vols.reshape(len(vols), -1)[:, ball.reshape(-1)]).astype(np.float64)
+    return F @ np.abs(P.real), F @ np.abs(P.imag)
 
 
 def test_expand_empty_batch_and_shape_errors():
