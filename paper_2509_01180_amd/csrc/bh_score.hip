@@ -447,9 +447,11 @@ __global__ __launch_bounds__(64) void k_newton_init(const double* __restrict__ s
 }
 
 // part[group][sp][k][lane]: score, gradient and Hessian sums of part sp of
-// the classes at the trial rotations.
+// the classes at the trial rotations.  Two waves per SIMD leave the Hessian
+// evaluator its ~210 registers (at four it spilled 176 bytes per lane and
+// ran 30 % longer).
 template <int G>
-__global__ __launch_bounds__(64 * kNewtonWaves) BH_HESS_OCCUPANCY(true) void k_newton_part(
+__global__ __launch_bounds__(64 * kNewtonWaves) __attribute__((amdgpu_waves_per_eu(2))) void k_newton_part(
     const int32_t* __restrict__ p_first, const int32_t* __restrict__ wave_p,
     const double* __restrict__ rec, const double* __restrict__ X, int64_t n_entries, int L,
     int64_t B, int P, const double* __restrict__ trial, double* __restrict__ part) {
