@@ -36,8 +36,10 @@ struct Angles {
   double ic2, is2;       // 1 / (4 c^2), 1 / (4 s^2)
   double msb;            // -sin(beta) = -2 s c (with the floored c, s)
   double sigma;          // (alpha + gamma) / 2
+  cplx e1;               // e^{-i sigma}
   cplx th1, th2;         // e^{-i delta}, e^{-2 i delta}, delta = (alpha - gamma) / 2
 };
+constexpr int kAngleWords = 13;   // doubles in Angles
 
 // Half-angle sines and cosines are kept at least this large in magnitude
 // (sign preserved) so that the x-derivative seeds below (up to 1 / s^4 for
@@ -45,23 +47,48 @@ struct Angles {
 // to any score is far below rounding.
 constexpr double kPoleFloor = 1e-30;
 
+// Three sincos per rotation: cos(beta) = 1 - 2 sin^2(beta/2) and
+// e^{-2 i delta} = (e^{-i delta})^2 follow from the half angles.
 BH_HD inline Angles prep(double al, double be, double ga) {
   Angles A;
-  double sb;
-  sincos(be, &sb, &A.x);
-  sincos(0.5 * be, &A.s, &A.c);
-  A.s = copysign(fmax(fabs(A.s), kPoleFloor), A.s);
-  A.c = copysign(fmax(fabs(A.c), kPoleFloor), A.c);
+  double s, c;
+  sincos(0.5 * be, &s, &c);
+  A.x = fma(-2.0 * s, s, 1.0);
+  A.s = copysign(fmax(fabs(s), kPoleFloor), s);
+  A.c = copysign(fmax(fabs(c), kPoleFloor), c);
   A.ic2 = 0.25 / (A.c * A.c);
   A.is2 = 0.25 / (A.s * A.s);
   A.msb = -2.0 * A.s * A.c;
   A.sigma = 0.5 * (al + ga);
-  const double delta = 0.5 * (al - ga);
-  double sd, cd, s2d, c2d;
-  sincos(delta, &sd, &cd);
-  sincos(2.0 * delta, &s2d, &c2d);
+  double ss, cs;
+  sincos(A.sigma, &ss, &cs);
+  A.e1 = {cs, -ss};
+  double sd, cd;
+  sincos(0.5 * (al - ga), &sd, &cd);
   A.th1 = {cd, -sd};
-  A.th2 = {c2d, -s2d};
+  A.th2 = cmul(A.th1, A.th1);
+  return A;
+}
+
+// Angles <-> kAngleWords doubles at stride `ld` (lane-major LDS rows).
+BH_HD inline void store_angles(const Angles& A, double* p, int ld) {
+  const double v[kAngleWords] = {A.x,     A.c,      A.s,      A.ic2,    A.is2,
+                                 A.msb,   A.sigma,  A.e1.re,  A.e1.im,  A.th1.re,
+                                 A.th1.im, A.th2.re, A.th2.im};
+  for (int k = 0; k < kAngleWords; ++k) p[k * ld] = v[k];
+}
+BH_HD inline Angles load_angles(const double* p, int ld) {
+  Angles A;
+  A.x = p[0];
+  A.c = p[ld];
+  A.s = p[2 * ld];
+  A.ic2 = p[3 * ld];
+  A.is2 = p[4 * ld];
+  A.msb = p[5 * ld];
+  A.sigma = p[6 * ld];
+  A.e1 = {p[7 * ld], p[8 * ld]};
+  A.th1 = {p[9 * ld], p[10 * ld]};
+  A.th2 = {p[11 * ld], p[12 * ld]};
   return A;
 }
 
@@ -144,9 +171,7 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
 #if !BH_SCORE_PHASE_SINCOS
   // Phi = e^{-i pc sigma} and cp = c^pc, advanced along the ascending
   // p-list one degree at a time.
-  double s1, c1;
-  sincos(A.sigma, &s1, &c1);
-  const cplx E1 = {c1, -s1};
+  const cplx E1 = A.e1;
   cplx Phi = {1.0, 0.0};
   double cp = 1.0;
   int pc = 0;

@@ -294,7 +294,9 @@ __device__ inline void newton_direction(double xb, double ga, double gb, double 
 //
 // Every evaluation is split over the W waves; the ascent state of the 64
 // lanes lives in LDS and is updated by wave 0 between two barriers, so the
-// other waves carry no optimiser state through the evaluation.  NEWTON:
+// other waves carry no optimiser state through the evaluation.  Wave 0 also
+// prepares the trial rotation's half-angle and phase factors once for all
+// waves (LDS `ang`).  NEWTON:
 // Newton steps from the Hessian (ST_ETA holds the damping mu <= 1).
 enum {
   ST_XA, ST_XB, ST_XG, ST_S, ST_GA, ST_GB, ST_GG, ST_ETA, ST_TA, ST_TB, ST_TG,
@@ -316,6 +318,7 @@ __global__ __launch_bounds__(64 * W) BH_MARCH_OCCUPANCY(NEWTON, G < 64) void k_m
   constexpr int NS = NEWTON ? ST_N : ST_HAA;
   __shared__ double red[W * NV * 64];
   __shared__ double st[NS * 64];
+  __shared__ double ang[kAngleWords * 64];   // the trial rotation's Angles, set by wave 0
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // Particles are taken in a grid-stride loop over blockIdx.y: one pass when
@@ -348,10 +351,11 @@ __global__ __launch_bounds__(64 * W) BH_MARCH_OCCUPANCY(NEWTON, G < 64) void k_m
       st[ST_TB * 64 + lane] = xb;
       st[ST_TG * 64 + lane] = xg;
       st[ST_ETA * 64 + lane] = NEWTON ? 1.0 : eta0;
+      store_angles(prep(xa, xb, xg), ang + lane, 64);
     }
     __syncthreads();
     for (int t = 0; t <= steps; ++t) {
-      const Angles A = prep(st[ST_TA * 64 + lane], st[ST_TB * 64 + lane], st[ST_TG * 64 + lane]);
+      const Angles A = load_angles(ang + lane, 64);
       const Acc mine = eval_wave<NEWTON>(A, wave_p + wave * (2 * L + 2), L, p_first, rec, Xp);
       store_partials<NV>(mine, red, wave, lane);
       __syncthreads();
@@ -405,6 +409,7 @@ __global__ __launch_bounds__(64 * W) BH_MARCH_OCCUPANCY(NEWTON, G < 64) void k_m
           st[ST_TA * 64 + lane] = ta;
           st[ST_TB * 64 + lane] = tb;
           st[ST_TG * 64 + lane] = tg;
+          store_angles(prep(ta, tb, tg), ang + lane, 64);
         }
       }
       __syncthreads();
