@@ -23,7 +23,9 @@
  * Band L: the frequency-ordered prefix {(k,l,m) : lambda_lk < lambda_{L+1,1}}.
  * Coefficient layout: radial entries (l,k) in ascending lambda (ties by
  *   (l,k)), each followed by m = -l..l; C(L) complex coefficients, stored
- *   interleaved (re, im) as float[2*C].  bh_index_table lists the order.
+ *   interleaved (re, im) as float[2*C], 8-byte aligned (the kernels read
+ *   each (re, im) pair at once; a misaligned coefficient pointer is
+ *   BH_EINVAL).  bh_index_table lists the order.
  * Coefficients: a_klm = h^3 sum_{|x_v|<1} conj(psi_klm(x_v)) f(x_v), h = 2/N
  *   (voxel quadrature of the L2 inner product).
  * Rotations: ZYZ Euler triples (alpha, beta, gamma), active,

@@ -155,6 +155,9 @@ int get_band(bh_plan* p, int L, const DevBand** out) {
 
 using namespace bh;
 
+// Coefficient arrays are read as (re, im) float pairs.
+static bool pairs_aligned(const float* q) { return ((uintptr_t)q & 7u) == 0; }
+
 extern "C" {
 
 const char* bh_last_error(void) { return g_err.c_str(); }
@@ -420,6 +423,8 @@ int bh_cross_power(bh_plan* p, const float* a, const float* b, int64_t B, int L,
   if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
   if (B == 0) return BH_OK;
   if (!a || !b || !xi) return set_error(BH_EINVAL, "NULL buffer");
+  if (!pairs_aligned(a) || !pairs_aligned(b))
+    return set_error(BH_EINVAL, "coefficient buffer not 8-byte aligned");
   return guarded([&]() -> int {
     DeviceGuard g(p->device);
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
@@ -439,6 +444,8 @@ static int correlate_common(bh_plan* p, const float* a, const float* b, int64_t 
   if (R < 1 || R > (1 << 20)) return set_error(BH_EINVAL, "rotation count out of range");
   if (B == 0) return BH_OK;
   if (!a || !b || !euler || !score) return set_error(BH_EINVAL, "NULL buffer");
+  if (!pairs_aligned(a) || !pairs_aligned(b))
+    return set_error(BH_EINVAL, "coefficient buffer not 8-byte aligned");
   return guarded([&]() -> int {
     DeviceGuard g(p->device);
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
@@ -468,6 +475,8 @@ int bh_degree_energy(bh_plan* p, const float* a, const float* b, int64_t B, int 
   if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
   if (B == 0) return BH_OK;
   if (!a || !b || !energy) return set_error(BH_EINVAL, "NULL buffer");
+  if (!pairs_aligned(a) || !pairs_aligned(b))
+    return set_error(BH_EINVAL, "coefficient buffer not 8-byte aligned");
   return guarded([&]() -> int {
     DeviceGuard g(p->device);
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
@@ -510,6 +519,8 @@ int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templat
   if (rc != BH_OK) return rc;
   if (B == 0) return BH_OK;
   if (!a || !templates || !starts || !euler_out || !score_out) return set_error(BH_EINVAL, "NULL buffer");
+  if (!pairs_aligned(a) || !pairs_aligned(templates))
+    return set_error(BH_EINVAL, "coefficient buffer not 8-byte aligned");
   return guarded([&]() -> int {
     DeviceGuard g(p->device);
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
@@ -531,6 +542,7 @@ int bh_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shi
   if (B == 0) return BH_OK;
   if (!vols || !b || !starts || !euler_out || !score_out || !shift_out)
     return set_error(BH_EINVAL, "NULL buffer");
+  if (!pairs_aligned(b)) return set_error(BH_EINVAL, "coefficient buffer not 8-byte aligned");
   int rc = check_align_opts(p, o);
   if (rc != BH_OK) return rc;
   return guarded([&]() -> int {
@@ -555,6 +567,8 @@ int bh_align_uneven(bh_plan* p, const float* a, int64_t lda, const int32_t* Lp,
   if (B == 0) return BH_OK;
   if (!a || !Lp || !templates || !starts || !euler_out || !score_out)
     return set_error(BH_EINVAL, "NULL buffer");
+  if (!pairs_aligned(a) || !pairs_aligned(templates))
+    return set_error(BH_EINVAL, "coefficient buffer not 8-byte aligned");
   for (int i = 1; i < o->n_bands; ++i)
     if (o->bands[i] <= o->bands[i - 1]) return set_error(BH_EINVAL, "bands must increase");
   for (int64_t i = 1; i < B; ++i)

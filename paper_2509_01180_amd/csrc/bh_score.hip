@@ -108,15 +108,14 @@ __global__ void k_xi_classes(const float* __restrict__ a, int64_t lda,
   if (e >= n_entries) return;
   const int l = sel[4 * e], m = sel[4 * e + 1], n = sel[4 * e + 2];
   const double w1 = wt[2 * e], w2 = wt[2 * e + 1];
-  const float* ap = a + pb * 2 * lda;
-  const float* b = btab + template_of(tmpl, n_tmpl, pb) * 2 * ldt;
+  const float2* ap = reinterpret_cast<const float2*>(a + pb * 2 * lda);
+  const float2* b = reinterpret_cast<const float2*>(btab + template_of(tmpl, n_tmpl, pb) * 2 * ldt);
   double x1r = 0, x1i = 0, x2r = 0, x2i = 0;
   for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
     const int o = deg_off[i];
-    const double bmr = b[2 * (o + l + m)], bmi = b[2 * (o + l + m) + 1];
-    const double bnr = b[2 * (o + l + n)], bni = b[2 * (o + l + n) + 1];
-    const double amr = ap[2 * (o + l + m)], ami = ap[2 * (o + l + m) + 1];
-    const double anr = ap[2 * (o + l + n)], ani = ap[2 * (o + l + n) + 1];
+    const float2 bm = b[o + l + m], bn = b[o + l + n], am = ap[o + l + m], an = ap[o + l + n];
+    const double bmr = bm.x, bmi = bm.y, bnr = bn.x, bni = bn.y;
+    const double amr = am.x, ami = am.y, anr = an.x, ani = an.y;
     x1r += bmr * anr + bmi * ani;      // conj(b_m) a_n
     x1i += bmr * ani - bmi * anr;
     x2r += bnr * amr + bni * ami;      // conj(b_n) a_m

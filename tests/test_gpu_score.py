@@ -124,4 +124,10 @@ def test_correlate_edge_batches():
     from paper_2509_01180_amd._lib import BhError
     with pytest.raises(BhError):
         plan.correlate(a1, b, 5, torch.zeros((1, 1, 3), dtype=torch.float64, device=dev))
+    # coefficient pairs must be 8-byte aligned: a view one float in is refused
+    raw = torch.zeros(2 * plan.C + 1, dtype=torch.float32, device=dev)
+    shifted = raw[1:].view(1, plan.C, 2)
+    assert shifted.data_ptr() % 8 == 4
+    with pytest.raises(BhError):
+        plan.correlate(shifted, b, 4, torch.zeros((1, 1, 3), dtype=torch.float64, device=dev))
     plan.close()
