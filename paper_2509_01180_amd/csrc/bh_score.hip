@@ -159,6 +159,68 @@ __global__ void k_band_weight(const float* __restrict__ a, int64_t lda,
   }
 }
 
+// k_xi_classes and k_band_weight in one pass, one block per particle: the
+// band's particle coefficients (the first C(L), at most kXiLdsCoeffs) are
+// staged in LDS, the template's come through the cache.  Same sums in the
+// same order as the two kernels above.
+constexpr int kXiLdsCoeffs = 7680;   // 60 KB of (re, im) pairs (L <= 40)
+
+__global__ __launch_bounds__(512) void k_xi_band(
+    const float* __restrict__ a, int64_t lda, const float* __restrict__ btab, int64_t ldt,
+    const int32_t* __restrict__ tmpl, int n_tmpl, int64_t n_entries,
+    const int32_t* __restrict__ sel, const double* __restrict__ wt,
+    const int32_t* __restrict__ deg_start, const int32_t* __restrict__ deg_off, int L, int CL,
+    double* __restrict__ X, double* __restrict__ Wb) {
+  extern __shared__ float2 sa[];   // [CL]
+  __shared__ double part[BH_MAX_L + 1];
+  const int tid = threadIdx.x;
+  const int64_t pb = blockIdx.x;
+  const float2* ap = reinterpret_cast<const float2*>(a + pb * 2 * lda);
+  const float2* b = reinterpret_cast<const float2*>(btab + template_of(tmpl, n_tmpl, pb) * 2 * ldt);
+  for (int i = tid; i < CL; i += blockDim.x) sa[i] = ap[i];
+  __syncthreads();
+  double* Xp = X + pb * n_entries * 4;
+  for (int64_t e = tid; e < n_entries; e += blockDim.x) {
+    const int l = sel[4 * e], m = sel[4 * e + 1], n = sel[4 * e + 2];
+    const double w1 = wt[2 * e], w2 = wt[2 * e + 1];
+    double x1r = 0, x1i = 0, x2r = 0, x2i = 0;
+    for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
+      const int o = deg_off[i];
+      const float2 bm = b[o + l + m], bn = b[o + l + n], am = sa[o + l + m], an = sa[o + l + n];
+      const double bmr = bm.x, bmi = bm.y, bnr = bn.x, bni = bn.y;
+      const double amr = am.x, ami = am.y, anr = an.x, ani = an.y;
+      x1r += bmr * anr + bmi * ani;      // conj(b_m) a_n
+      x1i += bmr * ani - bmi * anr;
+      x2r += bnr * amr + bni * ami;      // conj(b_n) a_m
+      x2i += bnr * ami - bni * amr;
+    }
+    double* out = Xp + e * 4;
+    out[0] = w1 * x1r;
+    out[1] = w1 * x1i;
+    out[2] = w2 * x2r;
+    out[3] = w2 * x2i;
+  }
+  for (int l = tid; l <= L; l += blockDim.x) {
+    double na = 0.0, nb = 0.0;
+    for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
+      const int o = deg_off[i];
+      for (int m = -l; m <= l; ++m) {
+        const float2 av = sa[o + l + m], bv = b[o + l + m];
+        const double ar = av.x, ai = av.y, br = bv.x, bi = bv.y;
+        na += ar * ar + ai * ai;
+        nb += br * br + bi * bi;
+      }
+    }
+    part[l] = (double)l * (l + 1) * sqrt(na) * sqrt(nb);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double w = 0.0;
+    for (int l = 0; l <= L; ++l) w += part[l];
+    Wb[pb] = w;
+  }
+}
+
 // Sum the W wave partials (fixed order) through LDS buffer `buf`
 // ([W][NV][64]); NV = 4 (score, gradient) or 10 (and the Hessian).
 template <int NV>
@@ -878,20 +940,39 @@ int launch_newton_split(int G, bh_plan* p, int64_t B, hipStream_t s, const DevBa
   return launch_newton_split_g<32>(p, B, s, band, X, Wb, P, steps, o, state, sscore);
 }
 
+// Class weights X of the band for B particles, and (Wb != NULL) the step
+// scale W_b of each.
 int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b,
                  const int32_t* tmpl, int n_tmpl, int64_t B, double** X, hipStream_t s,
-                 int64_t lda = 0, int64_t ldt = 0) {
+                 int64_t lda = 0, int64_t ldt = 0, double* Wb = nullptr) {
   if (lda <= 0) lda = p->C;
   if (ldt <= 0) ldt = p->C;
   // + kTablePad entries: the score loop reads up to three entries ahead
   int rc = grow(p->xi_scr, ((size_t)B * band.n_entries + kTablePad) * 4 * sizeof(double));
   if (rc != BH_OK) return rc;
   *X = (double*)p->xi_scr.ptr;
-  ProfScope ps(p, "xi_classes", s, B);
-  hipLaunchKernelGGL(k_xi_classes, dim3((unsigned)((band.n_entries + 127) / 128), (unsigned)B),
-                     dim3(128), 0, s, a, lda, b, ldt, tmpl, n_tmpl, band.n_entries, band.sel, band.wt,
-                     band.deg_start, band.deg_off, *X);
+  const int64_t CL = p->band_size[band.L];
+  if (Wb && CL <= kXiLdsCoeffs) {
+    ProfScope ps(p, "xi_classes", s, B);
+    hipLaunchKernelGGL(k_xi_band, dim3((unsigned)B), dim3(512), (size_t)CL * sizeof(float2), s, a,
+                       lda, b, ldt, tmpl, n_tmpl, band.n_entries, band.sel, band.wt,
+                       band.deg_start, band.deg_off, band.L, (int)CL, *X, Wb);
+    BH_HIP(hipGetLastError());
+    return BH_OK;
+  }
+  {
+    ProfScope ps(p, "xi_classes", s, B);
+    hipLaunchKernelGGL(k_xi_classes, dim3((unsigned)((band.n_entries + 127) / 128), (unsigned)B),
+                       dim3(128), 0, s, a, lda, b, ldt, tmpl, n_tmpl, band.n_entries, band.sel,
+                       band.wt, band.deg_start, band.deg_off, *X);
+  }
   BH_HIP(hipGetLastError());
+  if (Wb) {
+    ProfScope ps(p, "band_weight", s, B);
+    hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, lda, b, ldt, tmpl,
+                       n_tmpl, band.L, band.deg_start, band.deg_off, Wb);
+    BH_HIP(hipGetLastError());
+  }
   return BH_OK;
 }
 
@@ -966,13 +1047,8 @@ int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl
     B = active ? active[bi] : B_all;     // the particles that take this band
     if (B == 0) continue;
     double* X = nullptr;
-    if ((rc = prepare_band(p, *band, a, b, tmpl, n_tmpl, B, &X, s, lda, ldt)) != BH_OK) return rc;
-    {
-      ProfScope ps(p, "band_weight", s, B);
-      hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, lda, b, ldt, tmpl,
-                         n_tmpl, band->L, band->deg_start, band->deg_off, Wb);
-    }
-    BH_HIP(hipGetLastError());
+    if ((rc = prepare_band(p, *band, a, b, tmpl, n_tmpl, B, &X, s, lda, ldt, Wb)) != BH_OK)
+      return rc;
     // lanes per particle: 64, or fewer when the (pruned) restarts fit
     const int G = P <= 8 ? 8 : (P <= 16 ? 16 : (P <= 32 ? 32 : 64));
     const int64_t groups = (G == 64) ? (P + 63) / 64 * B : (B + 64 / G - 1) / (64 / G);
@@ -1078,9 +1154,7 @@ int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, 
     const DevBand* band = nullptr;
     if ((rc = get_band(p, bands[bi], &band)) != BH_OK) break;
     double* X = nullptr;
-    if ((rc = prepare_band(p, *band, a, b, nullptr, 1, B, &X, s)) != BH_OK) break;
-    hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, p->C, b, p->C,
-                       nullptr, 1, band->L, band->deg_start, band->deg_off, Wb);
+    if ((rc = prepare_band(p, *band, a, b, nullptr, 1, B, &X, s, 0, 0, Wb)) != BH_OK) break;
     float best_ms = 1e30f;
     int best_w = 0;
     p->tuned_persist[band->L] = 0;

@@ -143,3 +143,19 @@ def test_align_full_size_sampled():
         err = wigner.geodesic_deg(rot(eu[i]), w.truth(i).T)
         print(f"particle {i}: vs oracle {ang:.4f} deg, vs planted {err:.3f} deg")
         assert ang <= TOL_DEG
+
+
+def test_align_band_beyond_staged_size():
+    """A band of bandlimit 41 (C(41) = 7827 coefficients) takes the
+    unstaged cross-power path (bands up to 40 stage the particle's
+    coefficients in LDS); one band at 40 and one at 41 against the oracle."""
+    from test_gpu_score import random_real_coeffs
+    Lmax = 41
+    idx = basis.IndexSet(Lmax)
+    A = random_real_coeffs(idx, 1, 61)
+    b = random_real_coeffs(idx, 1, 62)[0]
+    rng = np.random.default_rng(63)
+    starts = synth.matrix_to_euler_zyz(synth.quat_to_matrix(synth.haar_quaternions(rng, 6)))[None]
+    bands = (40, 41)
+    eu, sc, ae, asc = gpu_align(16, Lmax, A, b, bands, starts, 3)
+    compare_particle(A[0], b, idx, bands, starts[0], 3, eu[0], sc[0], ae[0], asc[0])
