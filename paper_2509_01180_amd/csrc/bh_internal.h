@@ -170,7 +170,8 @@ int get_band(bh_plan* p, int L, const DevBand** out);
 // launchers (return BH_OK or an error code)
 int build_basis(bh_plan* p);
 // Split-K factor of the expansion GEMM: doubled while the grid has fewer
-// than 1024 tiles and each split keeps at least 8 K-steps.  With
+// than 2048 tiles (four waves of the 512 resident workgroups, so the last,
+// partial wave costs little) and each split keeps at least 8 K-steps.  With
 // batch_invariant the particle-tile count is taken as 8 (1024 particles)
 // whatever the batch, so a particle's sums never depend on the batch size.
 inline int expand_split(int64_t mt, int64_t nt, int64_t nk_total, bool batch_invariant,
@@ -181,7 +182,7 @@ inline int expand_split(int64_t mt, int64_t nt, int64_t nk_total, bool batch_inv
     if (it != tuned->end()) return it->second;
   }
   int nsplit = 1;
-  while (nsplit < 16 && mt * nt * nsplit < 1024 && (nk_total / (nsplit * 2)) >= 8) nsplit *= 2;
+  while (nsplit < 16 && mt * nt * nsplit < 2048 && (nk_total / (nsplit * 2)) >= 8) nsplit *= 2;
   return nsplit;
 }
 // Integer voxel shifts, passed to kernels by value.
