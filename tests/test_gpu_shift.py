@@ -33,10 +33,13 @@ def _planted(rng, bl, N, n):
     return np.stack(vols).astype(np.float32), truth
 
 
-def test_align_shifts_vs_oracle():
+@pytest.mark.parametrize("N", [20, 17])
+def test_align_shifts_vs_oracle(N):
+    """N = 17 puts ball voxels on the three mirror planes of the folded
+    expansion, where the shifted images of a voxel can coincide."""
     import torch
     from paper_2509_01180_amd.api import Plan
-    N, L = 20, 6
+    L = 6
     idx = basis.IndexSet(L)
     rng = np.random.default_rng(21)
     bl = synth.blob_template(rng, 8, radius=0.55)
