@@ -1,7 +1,7 @@
 """GPU parity of frequency marching + multi-start ascent (Sec. II-C).
 
 Same FP32 coefficients and starts on both sides; the best rotation must
-agree with the oracle's within 0.5 degrees (spec bar), unless the two
+agree with the oracle's within 0.5 degrees (the rotation bar of the plain path), unless the two
 winning restarts are a tie (scores within 1e-9 relative), in which case
 both must be maxima of equal score.  Most individual restart trajectories
 agree to rounding; accept/reject decisions at near-ties may split a few.
