@@ -217,9 +217,10 @@ class Plan:
                      steps: int, step_init: float = 1.0, step_grow: float = 1.25,
                      step_shrink: float = 0.5, return_all: bool = False,
                      batch_invariant: bool = False, newton_bands: int = 0, newton_steps: int = 0,
-                     keep: int = 0, min_sep: float = 0.0):
+                     keep: int = 0, min_sep: float = 0.0, out: tuple | None = None):
         """Particles of several bandlimits in one march (see bh_align_uneven):
-        a [B, lda, 2], Lp (B ints, non-increasing), templates [T, ldt, 2]."""
+        a [B, lda, 2], Lp (B ints, non-increasing), templates [T, ldt, 2].
+        out: optional (euler, score, all_euler, all_score) buffers to fill."""
         import numpy as np
         B, lda = a.shape[0], a.shape[1]
         T, ldt = templates.shape[0], templates.shape[1]
@@ -238,10 +239,19 @@ class Plan:
                       int(bool(batch_invariant)), int(newton_bands), int(newton_steps),
                       int(keep), float(min_sep))
         Po = keep if 0 < keep < P else P
-        eu = torch.empty((B, 3), dtype=torch.float64, device=a.device)
-        sc = torch.empty((B,), dtype=torch.float64, device=a.device)
-        ae = torch.empty((B, Po, 3), dtype=torch.float64, device=a.device) if return_all else None
-        asc = torch.empty((B, Po), dtype=torch.float64, device=a.device) if return_all else None
+        if out is None:
+            eu = torch.empty((B, 3), dtype=torch.float64, device=a.device)
+            sc = torch.empty((B,), dtype=torch.float64, device=a.device)
+            ae = torch.empty((B, Po, 3), dtype=torch.float64, device=a.device) if return_all else None
+            asc = torch.empty((B, Po), dtype=torch.float64, device=a.device) if return_all else None
+        else:
+            eu, sc, ae, asc = out
+            _dev(eu, torch.float64, (B, 3), "euler_out")
+            _dev(sc, torch.float64, (B,), "score_out")
+            if ae is not None:
+                _dev(ae, torch.float64, (B, Po, 3), "all_euler")
+            if asc is not None:
+                _dev(asc, torch.float64, (B, Po), "all_score")
         check(lib().bh_align_uneven(self._h, _ptr(a), lda, lp.ctypes.data_as(ctypes.c_void_p),
                                     _ptr(templates), ldt, T, _ptr(tmpl_idx), B, ctypes.byref(o),
                                     _ptr(starts), _ptr(eu), _ptr(sc), _ptr(ae), _ptr(asc),

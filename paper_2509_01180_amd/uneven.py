@@ -54,6 +54,16 @@ class UnevenAligner:
               batch_invariant: bool = False, **opts):
         """Best rotation and score per particle, returned per group in the
         order given: [(euler [n, 3], score [n]), ...]."""
+        a, Lp, tmpl, bands, starts, rows = self.pack(groups, mode, batch_invariant)
+        eu, sc = self.top.align_uneven(a, Lp, self.table, tmpl, bands, starts, steps,
+                                       batch_invariant=batch_invariant, **opts)
+        return [(eu[rows[i][0]:rows[i][1]], sc[rows[i][0]:rows[i][1]])
+                for i in range(len(groups))]
+
+    def pack(self, groups: Sequence[Group], mode: str = "fp32", batch_invariant: bool = False):
+        """The inputs of one uneven march: (a [n, ld, 2], Lp, template index
+        [n] int32, bands, starts [n, P, 3], {group: (first row, end row)}),
+        rows sorted by bandlimit."""
         torch = self.torch
         order = sorted(range(len(groups)), key=lambda i: -self.plans[groups[i].N].L_max)
         n_tot = sum(int(groups[i].vols.shape[0]) for i in order)
@@ -74,8 +84,4 @@ class UnevenAligner:
             r0 += n
         first = [b for b in self.bands if b <= min(Lp)]
         bands = [b for b in self.bands if b >= (first[0] if first else self.bands[0])]
-        eu, sc = self.top.align_uneven(a, Lp, self.table, torch.cat(tmpl).contiguous(), bands,
-                                       torch.cat(starts).contiguous(), steps,
-                                       batch_invariant=batch_invariant, **opts)
-        return [(eu[rows[i][0]:rows[i][1]], sc[rows[i][0]:rows[i][1]])
-                for i in range(len(groups))]
+        return (a, Lp, torch.cat(tmpl).contiguous(), bands, torch.cat(starts).contiguous(), rows)

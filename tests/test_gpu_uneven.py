@@ -85,3 +85,42 @@ def test_uneven_ordering_errors():
     torch.cuda.synchronize()
     assert torch.all(torch.isfinite(eu))
     plan.close()
+
+
+def test_uneven_graph_replays_match_eager():
+    """The uneven march captured once (GraphedAlignUneven) and replayed on
+    refilled inputs gives the eager call's bits on every replay."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd.graphs import GraphedAlignUneven
+    from paper_2509_01180_amd.uneven import Group, UnevenAligner
+    dev = cuda_device()
+    groups, tv = _data(dev)
+    plans = {N: Plan(N, L, device=0) for N, L in BOXES.items()}
+    tmpl = {N: plans[N].expand(torch.from_numpy(tv[N]).to(dev)) for N in BOXES}
+    ua = UnevenAligner(plans, tmpl, step=3)
+    say(f"uneven graph capture over boxes {sorted(BOXES)}")
+    sets = []
+    for flip in (False, True):
+        gs = []
+        for N in BOXES:
+            vols, t, st = groups[N]
+            gs.append(Group(N, torch.flip(vols, dims=(1,)).contiguous() if flip else vols, t,
+                            st.flip(1).contiguous() if flip else st))
+        sets.append(ua.pack(gs, batch_invariant=True))
+    a, Lp, ti, bands, st, _rows = sets[0]
+    a_buf, st_buf = a.clone(), st.clone()
+    g = GraphedAlignUneven(ua.top, a_buf, Lp, ua.table, ti, bands, st_buf, STEPS,
+                           batch_invariant=True)
+    ref = [ua.top.align_uneven(x[0], x[1], ua.table, x[2], x[3], x[4], STEPS, batch_invariant=True)
+           for x in sets]
+    torch.cuda.synchronize()
+    for rep in range(4):
+        k = rep % 2
+        a_buf.copy_(sets[k][0])
+        st_buf.copy_(sets[k][4])
+        eu, sc = g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(eu, ref[k][0]) and torch.equal(sc, ref[k][1]), rep
+    for p in plans.values():
+        p.close()
