@@ -159,3 +159,40 @@ def test_align_band_beyond_staged_size():
     bands = (40, 41)
     eu, sc, ae, asc = gpu_align(16, Lmax, A, b, bands, starts, 3)
     compare_particle(A[0], b, idx, bands, starts[0], 3, eu[0], sc[0], ae[0], asc[0])
+
+
+def test_precision_form_full_size_sampled():
+    """The precision form in the benchmark's launch shape: split-BF16
+    expansion of 1000 x 64^3, bands 8-24 on the BF16 coefficients, band 32
+    on the refined ones from every restart's end point; sampled particles
+    within 1 degree of the oracle's FP64 march (the precision form's bar)."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    w = synth.CONFIG2
+    dev = cuda_device()
+    sample = [5, 998]
+    rng = np.random.default_rng(15)
+    vols = (0.1 * rng.standard_normal((w.batch, w.N, w.N, w.N))).astype(np.float32)
+    for i in sample:
+        vols[i] = w.particle(i)
+    tv = w.template_volume()
+    starts = np.stack([w.starts(i) for i in range(w.batch)])
+    idx = basis.IndexSet(w.L_max)
+    ref_c = expand.expand(np.concatenate([tv[None], vols[sample]]).astype(np.float64), idx)
+    say("full-size precision form, B=1000, 64^3, L=32")
+    plan = Plan(w.N, w.L_max, device=0)
+    dv = torch.from_numpy(vols).to(dev)
+    coarse = torch.empty((w.batch, plan.C, 2), dtype=torch.float32, device=dev)
+    a = plan.expand_ex(dv, "bf16x3", coarse=coarse)
+    bt = plan.expand(torch.from_numpy(tv[None]).to(dev))[0].contiguous()
+    _e, _s, ends, _sc = plan.align(coarse, bt, w.bands[:-1], torch.from_numpy(starts).to(dev),
+                                   w.steps, return_all=True)
+    eu, sc = plan.align(a, bt, w.bands[-1:], ends, w.steps)
+    torch.cuda.synchronize()
+    eu = eu.cpu().numpy()
+    plan.close()
+    for j, i in enumerate(sample):
+        r = oalign.march(ref_c[1 + j], ref_c[0], idx, w.bands, starts[i], w.steps)
+        ang = wigner.geodesic_deg(rot(eu[i]), rot(r["euler"][r["best"]]))
+        print(f"particle {i}: precision form vs oracle {ang:.4f} deg")
+        assert ang <= 1.0
