@@ -196,3 +196,25 @@ def test_precision_form_full_size_sampled():
         ang = wigner.geodesic_deg(rot(eu[i]), rot(r["euler"][r["best"]]))
         print(f"particle {i}: precision form vs oracle {ang:.4f} deg")
         assert ang <= 1.0
+
+
+def test_align_option_limits():
+    """Options outside the ABI's limits are refused (no launch)."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd._lib import BhError
+    dev = cuda_device()
+    plan = Plan(16, 6, device=0)
+    a = torch.zeros((1, plan.C, 2), dtype=torch.float32, device=dev)
+    b = torch.zeros((plan.C, 2), dtype=torch.float32, device=dev)
+    st = torch.zeros((1, 4, 3), dtype=torch.float64, device=dev)
+    for bands, steps in [((7,), 2), (tuple(range(1, 18)), 1), ((3,), 10001), ((), 2)]:
+        with pytest.raises(BhError):
+            plan.align(a, b, bands, st, steps)
+    big = torch.zeros((1, 65537, 3), dtype=torch.float64, device=dev)
+    with pytest.raises(BhError):
+        plan.align(a, b, (3,), big, 1)
+    eu, sc = plan.align(a, b, (3, 6), st, 0)          # zero steps: the starts themselves
+    torch.cuda.synchronize()
+    assert torch.all(torch.isfinite(eu)) and torch.all(sc == 0)
+    plan.close()

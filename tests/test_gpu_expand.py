@@ -106,6 +106,12 @@ def test_expand_empty_batch_and_shape_errors():
         plan.expand(torch.zeros((2, 16, 16, 15), dtype=torch.float32, device=dev))
     with pytest.raises(TypeError):
         plan.expand(torch.zeros((2, 16, 16, 16), dtype=torch.float64, device=dev))
+    # sizes beyond the ABI's limits are refused before any memory is touched
+    from paper_2509_01180_amd._lib import BH_EINVAL, lib
+    small = torch.zeros((1, 16, 16, 16), dtype=torch.float32, device=dev)
+    coeffs = torch.zeros((1, plan.C, 2), dtype=torch.float32, device=dev)
+    assert lib().bh_expand(plan._h, small.data_ptr(), (1 << 21) + 1, coeffs.data_ptr(), None) == BH_EINVAL
+    assert lib().bh_expand(plan._h, small.data_ptr(), -1, coeffs.data_ptr(), None) == BH_EINVAL
     plan.close()
 
 
