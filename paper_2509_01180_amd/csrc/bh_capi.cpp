@@ -2,6 +2,7 @@
 // device selection and dispatch to the kernel launchers.
 #include <cstring>
 #include <exception>
+#include <memory>
 #include <new>
 #include <string>
 
@@ -96,8 +97,11 @@ ProfScope::ProfScope(bh_plan* p, const std::string& name, hipStream_t s, int64_t
     : p_(p), s_(s) {
   if (!p_->prof.on) return;
   hipEvent_t a = p_->prof.take(), b = p_->prof.take();
-  if (!a || !b) return;
-  if (hipEventRecord(a, s_) != hipSuccess) return;
+  if (!a || !b || hipEventRecord(a, s_) != hipSuccess) {   // keep the events for later
+    if (a) p_->prof.pool.push_back(a);
+    if (b) p_->prof.pool.push_back(b);
+    return;
+  }
   p_->prof.recs.push_back({name, a, b, work});
   idx_ = (int)p_->prof.recs.size() - 1;
 }
@@ -232,18 +236,16 @@ int bh_plan_create(int N, int L_max, int device, bh_plan** out) {
     if (device < 0 || device >= ndev) return set_error(BH_EINVAL, "device index out of range");
     DeviceGuard g(device);
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
-    bh_plan* p = new bh_plan();
+    // owned here until it is complete (an exception or error frees it)
+    std::unique_ptr<bh_plan, void (*)(bh_plan*)> p(new bh_plan(), bh_plan_destroy);
     p->N = N;
     p->L_max = L_max;
     p->device = device;
     p->idx = &index_set(L_max);
     for (int L = 0; L <= L_max; ++L) p->band_size.push_back(index_set(L).C);
-    int rc = build_basis(p);
-    if (rc != BH_OK) {
-      bh_plan_destroy(p);
-      return rc;
-    }
-    *out = p;
+    int rc = build_basis(p.get());
+    if (rc != BH_OK) return rc;
+    *out = p.release();
     return BH_OK;
   });
 }
