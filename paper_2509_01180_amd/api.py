@@ -108,6 +108,12 @@ class Plan:
         except Exception:
             pass
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def num_coeffs(self, L: int) -> int:
         return check(lib().bh_plan_num_coeffs(self._h, int(L)), "bh_plan_num_coeffs")
 
