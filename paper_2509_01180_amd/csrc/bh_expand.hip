@@ -111,29 +111,6 @@ __global__ __launch_bounds__(256) void k_gather_shift(const float* __restrict__ 
   }
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (linear id mod 8),
-// each with its own L2.  When the coefficient tiles divide evenly, XCD x
-// takes coefficient tiles [x*nt/8, (x+1)*nt/8) for every particle tile and
-// split, ordered so that co-resident workgroups share K-slices: particle
-// tiles fastest (they share the basis slice), then this XCD's coefficient
-// tiles (they share the volume slice), then splits.  Each basis column is
-// then fetched by one XCD only.
-__device__ inline void gemm_tile(int64_t bid, int64_t mt, int64_t nt, int64_t ns, int64_t& m,
-                                 int64_t& n, int64_t& sp) {
-  if (nt % 8 == 0) {
-    const int64_t xcd = bid % 8, local = bid / 8, ntx = nt / 8;
-    m = local % mt;
-    const int64_t r = local / mt;
-    n = xcd * ntx + r % ntx;
-    sp = r / ntx;
-  } else {
-    m = bid % mt;
-    const int64_t r = bid / mt;
-    n = r % nt;
-    sp = r / nt;
-  }
-}
-
 // part[s][m][n] = sum_{k in split s} Ft[k][m] Psi[k][n].
 // 4 waves in a 2x2 arrangement, each 64x64 = 2x2 MFMA 32x32 tiles.
 // MFMA 32x32x2 f32 operand layout: lane L supplies A[L%32][L/32] and

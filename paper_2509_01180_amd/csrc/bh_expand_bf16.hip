@@ -90,23 +90,6 @@ __global__ __launch_bounds__(256) void k_gather_split(const float* __restrict__ 
   }
 }
 
-// Tile placement over the XCDs, as for the FP32 GEMM (see bh_expand.hip).
-__device__ inline void tile_of(int64_t bid, int64_t mt, int64_t nt, int64_t ns, int64_t& m,
-                               int64_t& n, int64_t& sp) {
-  if (nt % 8 == 0) {
-    const int64_t xcd = bid % 8, local = bid / 8, ntx = nt / 8;
-    m = local % mt;
-    const int64_t r = local / mt;
-    n = xcd * ntx + r % ntx;
-    sp = r / ntx;
-  } else {
-    m = bid % mt;
-    const int64_t r = bid / mt;
-    n = r % nt;
-    sp = r / nt;
-  }
-}
-
 // COARSE: part_c += Fh Ph^T.  CORR: part_r += Fh Pl^T + Fl Ph^T.
 template <bool COARSE, bool CORR>
 __global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict__ fh,
@@ -124,7 +107,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict
   __shared__ __attribute__((aligned(16))) uint16_t Bl[LO ? 2 : 1][LO ? BN : 1][ROW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t tm, tn, ts;
-  tile_of(blockIdx.x, M_pad / BM, C_pad / BN, nsplit, tm, tn, ts);
+  gemm_tile(blockIdx.x, M_pad / BM, C_pad / BN, nsplit, tm, tn, ts);
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t k_begin = ts * (int64_t)nk * BK;
   // global -> LDS: 128 rows x 32 voxels = 512 chunks of 8 BF16; two per thread

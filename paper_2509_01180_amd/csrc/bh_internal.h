@@ -52,6 +52,26 @@ __host__ __device__ inline int class_of_tile(const ClassTiles& ct, int64_t tn) {
   return c;
 }
 
+// Placement of the expansion GEMM's tiles.  Workgroups are dispatched
+// round-robin over the 8 XCDs (linear id mod 8), each with its own L2.  The
+// tiles are ordered (split, coefficient tile, particle tile), particle tiles
+// fastest, and XCD x takes the x-th contiguous eighth of that order (the
+// first total % 8 XCDs one tile more).  Co-resident workgroups of an XCD then
+// work on one K-slice: those of one coefficient tile share its basis slice,
+// those of neighbouring coefficient tiles (mostly one parity class) the
+// folded-volume slice, and each slice is fetched by one XCD (two where a
+// boundary falls) instead of by all eight.
+__device__ inline void gemm_tile(int64_t bid, int64_t mt, int64_t nt, int64_t ns, int64_t& m,
+                                 int64_t& n, int64_t& sp) {
+  const int64_t total = mt * nt * ns, q = total / 8, rem = total % 8;
+  const int64_t xcd = bid % 8, local = bid / 8;
+  const int64_t g = xcd * q + (xcd < rem ? xcd : rem) + local;
+  m = g % mt;
+  const int64_t u = g / mt;
+  n = u % nt;
+  sp = u / nt;
+}
+
 // The 8 mirror images of voxel (i, j, k): image s (bit 0: i -> N-1-i,
 // bit 1: j, bit 2: k) at linear offset off[s].
 __device__ inline void mirror_offsets(int32_t lin, int N, int32_t off[8]) {
