@@ -360,6 +360,280 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
   }
   return acc;
 }
+
+// ------------------------------------------------- staged packed Hessian --
+//
+// The packed Newton evaluator (64 / G particles per wave, G lanes each)
+// reads its weights X from an LDS ring that LDS-DMA loads fill several
+// blocks ahead.  A block is four chain entries of every particle of the
+// wave (64 / G x 128 bytes, one DMA instruction); blocks follow the wave's
+// classes in evaluation order, each class starting a new block.  In a
+// block, particle g's 16-byte chunk j sits at g * 128 + (j ^ g) * 16, so the
+// reads of one entry by the wave's particles hit distinct bank groups.
+// Vector loads return in order, so "this block has landed" is a wait for
+// the number of blocks issued after it.
+template <int G>
+struct XRing {
+  static constexpr int PER = 64 / G;
+  static constexpr int kBlocks = 8, kAhead = kBlocks - 1, kBlockBytes = 1024;
+  char* ring;                 // this wave's kBlocks blocks of LDS
+  const char* src;            // DMA source of this lane (lanes < 8 PER): its particle and chunk
+  bool dma_lane;
+  const int32_t* plist;
+  const int32_t* p_first;
+  int L, np;
+  int ij, ip, iq, ioff, in, ik;   // issue position: p-list index, p, q, class offset and size, block
+  int issued, consumed;
+
+  __device__ void start(char* ring_, const double* X, int64_t n_entries, int64_t pb0, int64_t B,
+                        const int32_t* plist_, const int32_t* p_first_, int L_) {
+    ring = ring_;
+    plist = plist_;
+    p_first = p_first_;
+    L = L_;
+    np = plist[0];
+    const int lane = (int)(threadIdx.x & 63);
+    const int g = lane >> 3, j = (lane & 7) ^ (g & 7);
+    dma_lane = g < PER;
+    int64_t pd = pb0 + (dma_lane ? g : 0);
+    if (pd > B - 1) pd = B - 1;
+    src = reinterpret_cast<const char*>(X + pd * n_entries * 4) + 16 * j;
+    issued = consumed = 0;
+    ij = 0;
+    if (np > 0) {
+      ip = plist[1];
+      iq = ip & 1;
+      ioff = p_first[ip];
+      in = L - ((ip + iq) >> 1) + 1;
+      ik = 0;
+    }
+    while (issued < kAhead && ij < np) issue();
+  }
+  __device__ void issue() {
+    typedef __attribute__((address_space(1))) void global_void;
+    typedef __attribute__((address_space(3))) void lds_void;
+    char* dst = ring + (issued % kBlocks) * kBlockBytes;
+    if (dma_lane)
+      __builtin_amdgcn_global_load_lds((global_void*)(src + (int64_t)(ioff + 4 * ik) * 32),
+                                       (lds_void*)dst, 16, 0, 0);
+    ++issued;
+    if (4 * ++ik < in) return;
+    ik = 0;
+    ioff += in;
+    iq += 2;
+    if (iq > 2 * L - ip) {
+      if (++ij >= np) return;
+      ip = plist[1 + ij];
+      iq = ip & 1;
+      ioff = p_first[ip];
+    }
+    in = L - ((ip + iq) >> 1) + 1;
+  }
+  // The next block in evaluation order, landed; first tops up the ring
+  // (the slot refilled is the block consumed last, whose reads returned
+  // before ring_block finished).
+  __device__ const char* next() {
+    if (ij < np) issue();
+    const int younger = issued - consumed - 1;
+    switch (younger) {   // kAhead == 7
+      case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+      case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+      case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+      case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
+      case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+      case 5: asm volatile("s_waitcnt vmcnt(5)" ::: "memory"); break;
+      case 6: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
+      default: asm volatile("s_waitcnt vmcnt(7)" ::: "memory"); break;
+    }
+    const char* b = ring + (consumed % kBlocks) * kBlockBytes;
+    ++consumed;
+    return b;
+  }
+};
+static_assert(XRing<8>::kAhead == 7, "the wait table covers 0..7 younger blocks");
+
+// The four entries of a block for particle gq of the wave.  The reads are
+// written out, with their wait, because the compiler would otherwise wait
+// for every LDS-DMA load in flight before any read of the ring.
+struct Block4 {
+  double4 x[4];
+};
+__device__ inline Block4 ring_block(const char* blk, int gq) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(3))) const char lds_char;
+  const uint32_t base = (uint32_t)(uintptr_t)(lds_char*)(blk + gq * 128);
+  uint32_t a[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) a[c] = base + (uint32_t)((c ^ gq) * 16);
+  d2 v0, v1, v2, v3, v4, v5, v6, v7;
+  asm volatile(
+      "ds_read_b128 %0, %8\n\t"
+      "ds_read_b128 %1, %9\n\t"
+      "ds_read_b128 %2, %10\n\t"
+      "ds_read_b128 %3, %11\n\t"
+      "ds_read_b128 %4, %12\n\t"
+      "ds_read_b128 %5, %13\n\t"
+      "ds_read_b128 %6, %14\n\t"
+      "ds_read_b128 %7, %15\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=v"(v0), "=v"(v1), "=v"(v2), "=v"(v3), "=v"(v4), "=v"(v5), "=v"(v6), "=v"(v7)
+      : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7])
+      : "memory");
+  Block4 b;
+  b.x[0] = {v0.x, v0.y, v1.x, v1.y};
+  b.x[1] = {v2.x, v2.y, v3.x, v3.y};
+  b.x[2] = {v4.x, v4.y, v5.x, v5.y};
+  b.x[3] = {v6.x, v6.y, v7.x, v7.y};
+  return b;
+}
+
+// eval_wave<true> with the weights from the ring (same arithmetic, same order).
+template <int G>
+__device__ inline Acc eval_wave_staged(const Angles& A, const int32_t* __restrict__ plist, int L,
+                                       const int32_t* __restrict__ p_first,
+                                       const double* __restrict__ rec, XRing<G>& xr) {
+  constexpr bool HESS = true;
+  Acc acc = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int np = plist[0];
+  const int gq = (int)(threadIdx.x & 63) / G;
+  const cplx E1 = A.e1;
+  cplx Phi = {1.0, 0.0};
+  int pc = 0;
+  const double s2 = A.s * A.s;
+  const cplx th2c = {A.th2.re, -A.th2.im};
+  double qsum = 0.0, zpx = 0.0, zgx = 0.0;
+  const double mx = -A.x;
+  double cw[5] = {0.0, 0.0, 1.0, A.c, A.c * A.c};
+  int pw = 0;
+  for (int j = 0; j < np; ++j) {
+    const int p = plist[1 + j];
+    for (; pc < p; ++pc) Phi = cmul(Phi, E1);
+    for (; pw < p; ++pw) {
+      cw[0] = cw[1];
+      cw[1] = cw[2];
+      cw[2] = cw[3];
+      cw[3] = cw[4];
+      cw[4] *= A.c;
+    }
+    int off = p_first[p];
+    const int q0 = p & 1;
+    cplx W1 = q0 ? cmul(Phi, A.th1) : Phi;
+    cplx W2 = q0 ? cmulc(Phi, A.th1) : Phi;
+    double qd = (double)q0;
+    double SP = 0.0, SQ = 0.0;
+    double A0 = 0.0, A2 = 0.0, B1 = 0.0, ZP = 0.0, ZQ = 0.0;
+    double sw[5] = {0.0, q0 ? 1.0 : 0.0, q0 ? A.s : 1.0, q0 ? s2 : A.s, q0 ? s2 * A.s : s2};
+    for (int q = q0; q <= 2 * L - p; q += 2) {
+      const int m = (p + q) >> 1;
+      const int n = L - m + 1;        // chain entries
+      const double2* Rc = reinterpret_cast<const double2*>(rec) + off;
+      const double pd = (double)p;
+      double eb = cw[2] * sw[2];
+      double rb = 0.5 * (qd * cw[3] * sw[1] - pd * cw[1] * sw[3]);
+      double qb = 0.25 * (qd * (qd - 1.0) * cw[4] * sw[0] + pd * (pd - 1.0) * cw[0] * sw[4] -
+                          (qd * (pd + 1.0) + pd * (qd + 1.0)) * eb);
+      double t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i, ea, ra, qa;
+      double q1r, q1i, q2r, q2i;
+      Block4 xb = ring_block(xr.next(), gq);
+      {
+        const double4 x0 = xb.x[0];
+        const double2 c0_ = Rc[0];
+        t1r = x0.x * eb;
+        t1i = x0.y * eb;
+        t2r = x0.z * eb;
+        t2i = x0.w * eb;
+        r1r = x0.x * rb;
+        r1i = x0.y * rb;
+        r2r = x0.z * rb;
+        r2i = x0.w * rb;
+        const double u_ = c0_.x * (A.x - c0_.y);
+        ea = u_ * eb;
+        q1r = x0.x * qb;
+        q1i = x0.y * qb;
+        q2r = x0.z * qb;
+        q2i = x0.w * qb;
+        const double du_ = c0_.x * A.msb;
+        qa = fma(c0_.x * mx, eb, fma(du_ + du_, rb, u_ * qb));
+        ra = fma(du_, eb, u_ * rb);
+      }
+      for (int i0 = 0; i0 < n; i0 += 4) {
+        if (i0 > 0) {
+          xb = ring_block(xr.next(), gq);
+          const double4 x0 = xb.x[0];
+          const double2 c0_ = Rc[i0];
+          BH_CHAIN_STEP(x0, c0_, eb, rb, qb, ea, ra, qa);
+        }
+        if (i0 + 1 < n) {
+          const double4 x1 = xb.x[1];
+          const double2 c1 = Rc[i0 + 1];
+          BH_CHAIN_STEP(x1, c1, ea, ra, qa, eb, rb, qb);
+        }
+        if (i0 + 2 < n) {
+          const double4 x2 = xb.x[2];
+          const double2 c2 = Rc[i0 + 2];
+          BH_CHAIN_STEP(x2, c2, eb, rb, qb, ea, ra, qa);
+        }
+        if (i0 + 3 < n) {
+          const double4 x3 = xb.x[3];
+          const double2 c3 = Rc[i0 + 3];
+          BH_CHAIN_STEP(x3, c3, ea, ra, qa, eb, rb, qb);
+        }
+      }
+      const double z1 = fma(W1.re, t1r, -W1.im * t1i);
+      const double z2 = fma(W2.re, t2r, -W2.im * t2i);
+      const double zs = z1 + z2;
+      acc.S += zs;
+      A0 += zs;
+      A2 = fma(qd * qd, zs, A2);
+      B1 = fma(qd, z1 - z2, B1);
+      const double y1 = fma(W1.re, r1i, W1.im * r1r);
+      const double y2 = fma(W2.re, r2i, W2.im * r2r);
+      ZP += y1 + y2;
+      ZQ = fma(qd, y1 - y2, ZQ);
+      qsum = fma(W1.re, q1r, qsum);
+      qsum = fma(-W1.im, q1i, qsum);
+      qsum = fma(W2.re, q2r, qsum);
+      qsum = fma(-W2.im, q2i, qsum);
+      SP = fma(W1.re, t1i, SP);
+      SP = fma(W1.im, t1r, SP);
+      SP = fma(W2.re, t2i, SP);
+      SP = fma(W2.im, t2r, SP);
+      double D = W1.re * t1i;
+      D = fma(W1.im, t1r, D);
+      D = fma(-W2.re, t2i, D);
+      D = fma(-W2.im, t2r, D);
+      SQ = fma(qd, D, SQ);
+      acc.gb = fma(W1.re, r1r, acc.gb);
+      acc.gb = fma(-W1.im, r1i, acc.gb);
+      acc.gb = fma(W2.re, r2r, acc.gb);
+      acc.gb = fma(-W2.im, r2i, acc.gb);
+      off += n;
+      W1 = cmul(W1, A.th2);
+      W2 = cmul(W2, th2c);
+      qd += 2.0;
+      sw[0] = sw[2];
+      sw[1] = sw[3];
+      sw[2] = sw[4];
+      sw[3] *= s2;
+      sw[4] *= s2;
+    }
+    const double pd = (double)p;
+    const double pSP = pd * SP;
+    acc.ga += 0.5 * (pSP + SQ);
+    acc.gg += 0.5 * (pSP - SQ);
+    const double pp = pd * pd * A0;
+    acc.haa -= 0.25 * (pp + A2 + 2.0 * pd * B1);
+    acc.hgg -= 0.25 * (pp + A2 - 2.0 * pd * B1);
+    acc.hag -= 0.25 * (pp - A2);
+    zpx += 0.5 * (pd * ZP + ZQ);
+    zgx += 0.5 * (pd * ZP - ZQ);
+  }
+  acc.hab = zpx;
+  acc.hbg = zgx;
+  acc.hbb = qsum;
+  return acc;
+}
+
 #undef BH_CHAIN_STEP
 
 }  // namespace bh

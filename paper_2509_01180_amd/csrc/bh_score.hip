@@ -523,6 +523,7 @@ __global__ __launch_bounds__(64 * kNewtonWaves) __attribute__((amdgpu_waves_per_
     int64_t B, int P, const double* __restrict__ trial, double* __restrict__ part) {
   constexpr int W = kNewtonWaves, NV = 10, PER = 64 / G;
   __shared__ double red[W * NV * 64];
+  __shared__ __attribute__((aligned(1024))) char xring[W][XRing<G>::kBlocks * XRing<G>::kBlockBytes];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sp = blockIdx.x;
@@ -539,8 +540,10 @@ __global__ __launch_bounds__(64 * kNewtonWaves) __attribute__((amdgpu_waves_per_
     ga = t[2];
   }
   const Angles A = prep(al, be, ga);
-  const Acc mine = eval_wave<true>(A, wave_p + (sp * W + wave) * (2 * L + 2), L, p_first, rec,
-                                   X + pb * n_entries * 4);
+  const int32_t* plist = wave_p + (sp * W + wave) * (2 * L + 2);
+  XRing<G> xr;
+  xr.start(xring[wave], X, n_entries, grp * PER, B, plist, p_first, L);
+  const Acc mine = eval_wave_staged<G>(A, plist, L, p_first, rec, xr);
   store_partials<NV>(mine, red, wave, lane);
   __syncthreads();
   if (wave == 0) {
