@@ -132,6 +132,21 @@ def test_candidates_vs_oracle():
         _compare(r, eu[i], sc[i], ae[i], asc[i], min_agree=0.66)
 
 
+def test_candidates_sixteen_lane_groups_vs_oracle():
+    """Keeping 12 candidates packs 4 particles per wave (16 lanes each);
+    with 3 particles one lane group of the wave is idle."""
+    w, idx, A, b, starts = _workload(3, 17)
+    bands = (4, 8)
+    sep = np.radians(10.0)
+    eu, sc, ae, asc = _gpu_align(w, A, b, bands, starts, 12, keep=12, min_sep=sep,
+                                 newton_bands=1, newton_steps=5)
+    assert ae.shape == (3, 12, 3) and asc.shape == (3, 12)
+    for i in range(len(A)):
+        r = oalign.march(A[i], b, idx, bands, starts[i], 12, keep=12, min_sep=sep,
+                         newton_bands=1, newton_steps=5)
+        _compare(r, eu[i], sc[i], ae[i], asc[i], min_agree=0.66)
+
+
 def test_keep_edge_cases():
     import torch
     from paper_2509_01180_amd.api import Plan
