@@ -513,9 +513,10 @@ __global__ __launch_bounds__(64) void k_newton_init(const double* __restrict__ s
 }
 
 // part[group][sp][k][lane]: score, gradient and Hessian sums of part sp of
-// the classes at the trial rotations.  Two waves per SIMD leave the Hessian
-// evaluator its ~210 registers (at four it spilled 176 bytes per lane and
-// ran 30 % longer).
+// the classes at the trial rotations, the weights staged through an LDS
+// ring per wave (XRing).  Two waves per SIMD leave the Hessian evaluator
+// its ~190 registers (at three it spilled 72 bytes per lane and ran 4 %
+// longer).
 template <int G>
 __global__ __launch_bounds__(64 * kNewtonWaves) __attribute__((amdgpu_waves_per_eu(2))) void k_newton_part(
     const int32_t* __restrict__ p_first, const int32_t* __restrict__ wave_p,
