@@ -16,12 +16,12 @@
 //                 column tile reads the slice of its class
 //   k_reduce2   : sums splits, scatters to the complex layout
 //
-// Operands are K-contiguous rows (particles, coefficients), staged in LDS
-// with rows padded to 40 BF16 (80 bytes) so that 16-byte fragment reads of
-// eight consecutive rows fall in distinct banks.  A lane's fragment is eight
-// consecutive voxels of one row; the same voxel-to-lane map is used for both
-// operands, so the sum over voxels is exact whatever order the instruction
-// takes it in.
+// Operands are K-contiguous rows (particles, coefficients), copied into LDS
+// by LDS-DMA loads with the 16-byte chunks of each row XOR-swizzled so that
+// fragment reads of eight consecutive rows fall in distinct banks.  A lane's
+// fragment is eight consecutive voxels of one row; the same voxel-to-lane map
+// is used for both operands, so the sum over voxels is exact whatever order
+// the instruction takes it in.
 #include "bh_internal.h"
 
 #include <algorithm>
@@ -32,7 +32,7 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 128, BN = 128, BK = 32, ROW = 40;
+constexpr int BM = 128, BN = 128, BK = 32;
 
 // FP32 -> BF16 bits, round to nearest even (inputs are finite).
 __device__ inline uint16_t bf16_bits(float x) {
@@ -90,7 +90,39 @@ __global__ __launch_bounds__(256) void k_gather_split(const float* __restrict__ 
   }
 }
 
+typedef __attribute__((address_space(1))) void global_void;
+typedef __attribute__((address_space(3))) void lds_void;
+
+// LDS of one K step: the 128 rows of Fh, Ph (and Fl, Pl with the
+// correction), 64 bytes each (four 16-byte chunks); two steps alternate.
+constexpr int kRowBytes = BK * 2, kArrBytes = BM * kRowBytes;   // BM == BN
+template <bool LO>
+struct StepLds {
+  static constexpr int ah = 0, bh = kArrBytes, al = 2 * kArrBytes, bl = 3 * kArrBytes;
+  static constexpr int bytes = (LO ? 4 : 2) * kArrBytes;
+};
+
+// Chunk c of row r sits at chunk position c ^ ((r >> 1) & 3): the 16-byte
+// fragment reads of eight consecutive rows then hit distinct bank groups.
+__device__ inline int step_swz(int c, int r) { return c ^ ((r >> 1) & 3); }
+
+// Wait for this wave's LDS reads and LDS-DMA loads, then the barrier.
+// (Written out: the compiler's barrier adds nothing here, and its own wait
+// placement does not know about the DMA loads.)
+__device__ inline void dma_barrier() {
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // COARSE: part_c += Fh Ph^T.  CORR: part_r += Fh Pl^T + Fl Ph^T.
+//
+// 4 waves in a 2 x 2 arrangement, each 64 x 64 as 2 x 2 MFMA tiles per
+// accumulator set.  The operands of K step kt + 1 are copied global -> LDS
+// by the waves' LDS-DMA loads (16 bytes per lane straight into LDS; a load
+// covers 16 rows of one array, lane i -> LDS bytes 16 i, the lane fetching
+// the chunk the swizzle places there) while step kt is computed; no
+// register staging, so the fragments of both 16-voxel halves of a step can
+// be read before its MFMAs run.  Only `smem` lives in LDS: with a second LDS
+// variable the compiler would wait for every DMA load before each read.
 template <bool COARSE, bool CORR>
 __global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict__ fh,
                                                       const uint16_t* __restrict__ fl,
@@ -101,68 +133,60 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict
                                                       int64_t C_pad, int64_t VR_pad, ClassTiles ct,
                                                       int nk, int nsplit) {
   constexpr bool LO = CORR;
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][BM][ROW];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][BN][ROW];
-  __shared__ __attribute__((aligned(16))) uint16_t Al[LO ? 2 : 1][LO ? BM : 1][ROW];
-  __shared__ __attribute__((aligned(16))) uint16_t Bl[LO ? 2 : 1][LO ? BN : 1][ROW];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  using St = StepLds<LO>;
+  __shared__ __attribute__((aligned(1024))) char smem[2 * St::bytes];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   int64_t tm, tn, ts;
   gemm_tile(blockIdx.x, M_pad / BM, C_pad / BN, nsplit, tm, tn, ts);
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t k_begin = ts * (int64_t)nk * BK;
-  // global -> LDS: 128 rows x 32 voxels = 512 chunks of 8 BF16; two per thread
-  const int r0 = tid >> 2, r1 = r0 + 64, cc = (tid & 3) * 8;
   const int64_t slab = class_of_tile(ct, tn) * M_pad * VR_pad;
-  const uint16_t* ga_h = fh + slab + (m0 + r0) * VR_pad + k_begin + cc;
-  const uint16_t* gb_h = ph + (n0 + r0) * VR_pad + k_begin + cc;
-  const uint16_t* ga_l = LO ? fl + slab + (m0 + r0) * VR_pad + k_begin + cc : nullptr;
-  const uint16_t* gb_l = LO ? pl + (n0 + r0) * VR_pad + k_begin + cc : nullptr;
-  const int64_t off64a = 64 * VR_pad, off64b = 64 * VR_pad;
-  uint4 xah0, xah1, xbh0, xbh1, xal0, xal1, xbl0, xbl1;
-#define BH_LOAD(kt)                                                                   \
-  do {                                                                                \
-    const int64_t ko = (int64_t)(kt) * BK;                                            \
-    xah0 = *reinterpret_cast<const uint4*>(ga_h + ko);                                \
-    xah1 = *reinterpret_cast<const uint4*>(ga_h + off64a + ko);                       \
-    xbh0 = *reinterpret_cast<const uint4*>(gb_h + ko);                                \
-    xbh1 = *reinterpret_cast<const uint4*>(gb_h + off64b + ko);                       \
-    if (LO) {                                                                         \
-      xal0 = *reinterpret_cast<const uint4*>(ga_l + ko);                              \
-      xal1 = *reinterpret_cast<const uint4*>(ga_l + off64a + ko);                     \
-      xbl0 = *reinterpret_cast<const uint4*>(gb_l + ko);                              \
-      xbl1 = *reinterpret_cast<const uint4*>(gb_l + off64b + ko);                     \
-    }                                                                                 \
-  } while (0)
-#define BH_STORE(buf)                                                                 \
-  do {                                                                                \
-    *reinterpret_cast<uint4*>(&Ah[buf][r0][cc]) = xah0;                               \
-    *reinterpret_cast<uint4*>(&Ah[buf][r1][cc]) = xah1;                               \
-    *reinterpret_cast<uint4*>(&Bh[buf][r0][cc]) = xbh0;                               \
-    *reinterpret_cast<uint4*>(&Bh[buf][r1][cc]) = xbh1;                               \
-    if (LO) {                                                                         \
-      *reinterpret_cast<uint4*>(&Al[LO ? buf : 0][LO ? r0 : 0][cc]) = xal0;           \
-      *reinterpret_cast<uint4*>(&Al[LO ? buf : 0][LO ? r1 : 0][cc]) = xal1;           \
-      *reinterpret_cast<uint4*>(&Bl[LO ? buf : 0][LO ? r0 : 0][cc]) = xbl0;           \
-      *reinterpret_cast<uint4*>(&Bl[LO ? buf : 0][LO ? r1 : 0][cc]) = xbl1;           \
-    }                                                                                 \
-  } while (0)
+  // DMA: wave w loads rows 32 w .. 32 w + 31 of each array as two blocks of
+  // 16 rows; lane -> row 32 w + lane / 4 (+ 16), stored chunk lane % 4
+  const int lrow = 32 * wave + (lane >> 2);
+  const int lchunk = step_swz(lane & 3, lrow);
+  const uint16_t* ga_h = fh + slab + (m0 + lrow) * VR_pad + k_begin + 8 * lchunk;
+  const uint16_t* gb_h = ph + (n0 + lrow) * VR_pad + k_begin + 8 * lchunk;
+  const uint16_t* ga_l = LO ? fl + slab + (m0 + lrow) * VR_pad + k_begin + 8 * lchunk : nullptr;
+  const uint16_t* gb_l = LO ? pl + (n0 + lrow) * VR_pad + k_begin + 8 * lchunk : nullptr;
+  const int64_t next16 = 16 * VR_pad;
+  const int dst = wave * 2048;
+  auto issue = [&](int kt) {
+    char* st = smem + (kt & 1) * St::bytes + dst;
+    const int64_t ko = (int64_t)kt * BK;
+    __builtin_amdgcn_global_load_lds((global_void*)(ga_h + ko), (lds_void*)(st + St::ah), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((global_void*)(ga_h + next16 + ko), (lds_void*)(st + St::ah + 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((global_void*)(gb_h + ko), (lds_void*)(st + St::bh), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((global_void*)(gb_h + next16 + ko), (lds_void*)(st + St::bh + 1024), 16, 0, 0);
+    if (LO) {
+      __builtin_amdgcn_global_load_lds((global_void*)(ga_l + ko), (lds_void*)(st + St::al), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((global_void*)(ga_l + next16 + ko), (lds_void*)(st + St::al + 1024), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((global_void*)(gb_l + ko), (lds_void*)(st + St::bl), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((global_void*)(gb_l + next16 + ko), (lds_void*)(st + St::bl + 1024), 16, 0, 0);
+    }
+  };
   floatx16 c00 = {}, c01 = {}, c10 = {}, c11 = {};
   floatx16 d00 = {}, d01 = {}, d10 = {}, d11 = {};
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int hl = lane >> 5, ll = lane & 31;
-  BH_LOAD(0);
-  BH_STORE(0);
-  __syncthreads();
+  // fragment rows wm + ll, wm + 32 + ll (A), wn + ll, wn + 32 + ll (B): the
+  // swizzle depends on ll only (wm, wn are multiples of 64)
+  const int fa0 = (wm + ll) * kRowBytes, fa1 = fa0 + 32 * kRowBytes;
+  const int fb0 = (wn + ll) * kRowBytes, fb1 = fb0 + 32 * kRowBytes;
+  issue(0);
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) BH_LOAD(kt + 1);
+    dma_barrier();                   // step kt landed; step kt - 1's buffer is free
+    if (kt + 1 < nk) issue(kt + 1);
+    const char* st = smem + (kt & 1) * St::bytes;
 #pragma unroll
     for (int ks = 0; ks < BK / 16; ++ks) {
-      const int kc = 16 * ks + 8 * hl;
-      const bf16x8 ah0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[cur][wm + ll][kc]));
-      const bf16x8 ah1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Ah[cur][wm + 32 + ll][kc]));
-      const bf16x8 bh0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[cur][wn + ll][kc]));
-      const bf16x8 bh1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bh[cur][wn + 32 + ll][kc]));
+      const int co = 16 * step_swz(2 * ks + hl, ll);
+      auto frag = [&](int off) {
+        return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(st + off + co));
+      };
+      const bf16x8 ah0 = frag(St::ah + fa0), ah1 = frag(St::ah + fa1);
+      const bf16x8 bh0 = frag(St::bh + fb0), bh1 = frag(St::bh + fb1);
       if (COARSE) {
         c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bh0, c00, 0, 0, 0);
         c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bh1, c01, 0, 0, 0);
@@ -170,10 +194,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict
         c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bh1, c11, 0, 0, 0);
       }
       if (CORR) {
-        const bf16x8 al0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[LO ? cur : 0][LO ? wm + ll : 0][kc]));
-        const bf16x8 al1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Al[LO ? cur : 0][LO ? wm + 32 + ll : 0][kc]));
-        const bf16x8 bl0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[LO ? cur : 0][LO ? wn + ll : 0][kc]));
-        const bf16x8 bl1 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bl[LO ? cur : 0][LO ? wn + 32 + ll : 0][kc]));
+        const bf16x8 al0 = frag(St::al + fa0), al1 = frag(St::al + fa1);
+        const bf16x8 bl0 = frag(St::bl + fb0), bl1 = frag(St::bl + fb1);
         d00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bl0, d00, 0, 0, 0);
         d01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, bl1, d01, 0, 0, 0);
         d10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah1, bl0, d10, 0, 0, 0);
@@ -184,11 +206,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict
         d11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al1, bh1, d11, 0, 0, 0);
       }
     }
-    if (kt + 1 < nk) BH_STORE(cur ^ 1);
-    __syncthreads();
   }
-#undef BH_LOAD
-#undef BH_STORE
   const int64_t row0 = m0 + wm + 4 * hl, col0 = n0 + wn + ll;
   float* oc = part_c + ts * M_pad * C_pad;
   float* orr = part_r + ts * M_pad * C_pad;
