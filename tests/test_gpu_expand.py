@@ -1,7 +1,9 @@
 """GPU parity of the expansion (Sec. II-A) against the FP64 oracle.
 
-Bar: per-particle normwise relative error <= 1e-5 (FP32 inputs, FP32 MFMA
-with split-K partial sums; the oracle sums the same FP32 samples in FP64).
+Bars: per-particle normwise relative error <= 1e-5 (FP32 inputs, FP32 MFMA
+with split-K partial sums; the oracle sums the same FP32 samples in FP64),
+and for the FP32 path each coefficient within the first-order rounding
+bound n 2^-24 sum_v |f psi| (assert_fp32_per_coefficient).
 Cases span several 128x128 tiles with ragged particle and coefficient
 tails, an odd box (centre voxel at r = 0), B = 0, and the full 64^3, L = 32,
 B = 1000 launch shape of the benchmark on sampled particles.
@@ -19,7 +21,7 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
-def run_gpu(N, L, vols):
+def run_gpu(N, L, vols, with_split=False):
     import torch
     from paper_2509_01180_amd.api import Plan
     dev = cuda_device()
@@ -28,8 +30,42 @@ def run_gpu(N, L, vols):
     out = plan.expand(torch.from_numpy(np.ascontiguousarray(vols, dtype=np.float32)).to(dev))
     torch.cuda.synchronize()
     got = to_complex(out)
+    split = plan.tuning(max(1, len(vols)))["split_f32"]
     plan.close()
-    return got
+    return (got, split) if with_split else got
+
+
+def fp32_terms(N, nsplit):
+    """Rounding steps on the way to one FP32 coefficient: the 8-image fold
+    (three levels of additions), the basis entry's FP32 storage, the longest
+    run of sequential FP32 accumulations in one split-K slice (the folded
+    voxel count, padded to 512, over the splits) and the sum of the splits."""
+    i = np.arange(N)
+    x = (i - (N - 1) / 2) * 2 / N
+    half = x[x >= -1e-12]          # one representative per mirror orbit (and the planes)
+    X, Y, Z = np.meshgrid(half, half, half, indexing="ij")
+    VR = int(((X ** 2 + Y ** 2 + Z ** 2) < 1).sum())
+    VR_pad = -(-VR // 512) * 512
+    return 3 + 1 + VR_pad // nsplit + nsplit
+
+
+def assert_fp32_per_coefficient(got, ref, vols, L, nsplit):
+    """Per-coefficient bar of the FP32 path: every rounding is relative to
+    the magnitude of the summed terms, so |a_gpu - a| <= n 2^-24 sum_v
+    |f(v)| |psi(v)| (first order, n = fp32_terms), for the real and the
+    imaginary part separately.  It holds whatever the cancellation in the
+    coefficient, so it also catches a single wrong coefficient far below
+    the normwise bar."""
+    sr, si = split_bf16_scale(vols, L)
+    n = fp32_terms(vols.shape[-1], nsplit)
+    d = got - ref
+    tol = 1.01 * n * 2.0 ** -24
+    rr = np.abs(d.real) / np.maximum(sr, 1e-300)
+    ri = np.abs(d.imag) / np.maximum(si, 1e-300)
+    print(f"per-coefficient error / (2^-24 sum|f psi|): max re {rr.max() / 2.0 ** -24:.1f}, "
+          f"im {ri.max() / 2.0 ** -24:.1f}; bound {n}")
+    assert np.all(np.abs(d.real) <= tol * sr + 1e-30)
+    assert np.all(np.abs(d.imag) <= tol * si + 1e-30)
 
 
 def test_expand_config1_volumes():
@@ -37,10 +73,11 @@ def test_expand_config1_volumes():
     vols = np.stack([w.template_volume(), w.particle(0), w.particle(1),
                      w.particle(2, wedge=False, noise=False)])
     ref = expand.expand(vols.astype(np.float64), basis.IndexSet(w.L_max))
-    got = run_gpu(w.N, w.L_max, vols)
+    got, split = run_gpu(w.N, w.L_max, vols, with_split=True)
     err = normwise(got, ref)
     print("normwise", err)
     assert np.all(err <= TOL)
+    assert_fp32_per_coefficient(got, ref, vols, w.L_max, split)
 
 
 def test_expand_ragged_tiles():
@@ -51,10 +88,11 @@ def test_expand_ragged_tiles():
     bl = synth.blob_template(rng, 10)
     vols[::7] += 3 * synth.render_blobs(bl, N).astype(np.float32)
     ref = expand.expand(vols.astype(np.float64), basis.IndexSet(L))
-    got = run_gpu(N, L, vols)
+    got, split = run_gpu(N, L, vols, with_split=True)
     err = normwise(got, ref)
     assert got.shape == ref.shape
     assert np.all(err <= TOL), err.max()
+    assert_fp32_per_coefficient(got, ref, vols, L, split)
 
 
 def test_expand_odd_box_and_low_bandlimit():
@@ -66,8 +104,9 @@ def test_expand_odd_box_and_low_bandlimit():
         rng = np.random.default_rng(N)
         vols = rng.standard_normal((5, N, N, N)).astype(np.float32)
         ref = expand.expand(vols.astype(np.float64), basis.IndexSet(L))
-        got = run_gpu(N, L, vols)
+        got, split = run_gpu(N, L, vols, with_split=True)
         assert np.all(normwise(got, ref) <= TOL)
+        assert_fp32_per_coefficient(got, ref, vols, L, split)
         plan = Plan(N, L, device=0)
         c3 = plan.expand_ex(torch.from_numpy(vols).to(cuda_device()), "bf16x3")
         torch.cuda.synchronize()
@@ -140,11 +179,12 @@ def test_expand_full_size_sampled():
     for i in sample:
         vols[i] = w.particle(i)
     ref = expand.expand(vols[sample].astype(np.float64), basis.IndexSet(w.L_max))
-    got = run_gpu(w.N, w.L_max, vols)
+    got, split = run_gpu(w.N, w.L_max, vols, with_split=True)
     err = normwise(got[sample], ref)
     print("normwise", err)
     assert np.all(err <= TOL)
     assert np.all(np.isfinite(got))
+    assert_fp32_per_coefficient(got[sample], ref, vols[sample], w.L_max, split)
 
 
 def test_expand_bf16_modes():
