@@ -110,6 +110,15 @@ void bh_plan_destroy(bh_plan* p);
 /* Complex coefficient count of the plan's band L (0 <= L <= L_max). */
 int64_t bh_plan_num_coeffs(const bh_plan* p, int L);
 
+/* Synchronise `stream`, then report errors that the plan's kernels found in
+ * device-side arguments since the last report: BH_EINVAL if a particle's
+ * template index (bh_align_t, bh_align_uneven) was outside the template
+ * table, else BH_OK.  Reporting clears the flag.  The flag lives in pinned
+ * host memory that the kernels write, so bh_align_t and bh_align_uneven
+ * also return it at entry (enqueuing nothing) once the offending call's
+ * kernels have run. */
+int bh_plan_check(bh_plan* p, void* stream);
+
 /* ---------------------------------------------------------------------
  * Expansion (Sec. II-A): volumes -> coefficients of band L_max.
  * vols:   dev float[B][N][N][N]
@@ -193,6 +202,30 @@ int bh_degree_energy(bh_plan* p, const float* a, const float* b, int64_t B, int 
                      double* energy, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Band selection by the energy ratio (Fig. 1 caption, Sec. III: the
+ * bandlimits of the march are where the cross-power energy left out by a
+ * truncation falls below thresholds).  For each particle b, against its
+ * template (tmpl_idx as in bh_align_t), with E_l = ||xi^l||_F^2 of the
+ * band-L_top cross-power:
+ *   Ratio_b(L') = sum_{L' < l <= L_top} E_l / sum_{l <= L_top} E_l
+ *   (0 where every E_l is 0; non-increasing in L', Ratio_b(L_top) = 0),
+ *   bands[b][j] = the smallest L' with Ratio_b(L') <= thresholds[j].
+ * For the batch, common[j] = the smallest L' with Ratio_b(L') <= tau_j for
+ * at least ceil(B/2) particles, i.e. the lower median of bands[.][j].  A
+ * march schedule is the distinct common[j] (above 0) in increasing order
+ * followed by L_top.
+ * thresholds: host double[n_tau], 1 <= n_tau <= 16, each in [0, 1]
+ * bands:      dev int32[B][n_tau]
+ * common:     dev int32[n_tau], or NULL
+ * ratio:      dev double[B][L_top + 1], or NULL
+ * A particle whose template index is outside the table gets NaN ratios and
+ * L_top for every threshold; the error is reported as for bh_align_t.
+ * ------------------------------------------------------------------- */
+int bh_select_bands(bh_plan* p, const float* a, const float* templates, int n_templates,
+                    const int32_t* tmpl_idx, int64_t B, int L_top, const double* thresholds,
+                    int n_tau, int32_t* bands, int32_t* common, double* ratio, void* stream);
+
+/* ---------------------------------------------------------------------
  * Alignment (Sec. II-C): frequency marching over `bands` with multi-start
  * gradient ascent.  For each band L_b (each <= L_max, any order): evaluate
  * (S, grad S) at the carried point x; step eta = step_init / W_b with
@@ -254,8 +287,13 @@ int bh_align(bh_plan* p, const float* a, const float* b, int64_t B,
 
 /* As bh_align, against one of several templates per particle:
  * templates: dev float[n_templates][C(L_max)][2]
- * tmpl_idx:  dev int32[B], template of each particle (values outside
- *            0..n_templates-1 are clamped); may be NULL if n_templates == 1.
+ * tmpl_idx:  dev int32[B], template of each particle, in 0..n_templates-1;
+ *            may be NULL if n_templates == 1.  The indices are device data,
+ *            so they are checked by the kernels: a particle with an index
+ *            outside the table gets a NaN score (its rotation is not
+ *            meaningful), no memory outside the table is read, and the
+ *            error is reported as BH_EINVAL by bh_plan_check or by a later
+ *            bh_align_t / bh_align_uneven call on the plan.
  * A call with one band and all_euler set advances every restart by one band
  * of the march; its all_euler output is the next call's starts. */
 int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templates,

@@ -143,6 +143,26 @@ def select_bands(ratio: np.ndarray, thresholds) -> list:
     return sorted(out)
 
 
+def select_bands_batch(ratios: np.ndarray, thresholds) -> list:
+    """The batch's band for each threshold tau (in the order given): the
+    smallest L with Ratio_b(L) <= tau for at least ceil(B/2) of the B
+    particles' ratio curves ``ratios[b]`` (the paper picks one band set for
+    a data set, Sec. III; half of the particles is the reading taken for
+    "the data set").  Counted by brute force over L and b."""
+    r = np.asarray(ratios, dtype=np.float64)
+    B, n = r.shape
+    need = (B + 1) // 2
+    out = []
+    for tau in thresholds:
+        pick = n - 1
+        for L in range(n):
+            if sum(1 for b in range(B) if r[b, L] <= tau) >= need:
+                pick = L
+                break
+        out.append(pick)
+    return out
+
+
 def band_norms(a: np.ndarray, b: np.ndarray, idx: IndexSet, L: int):
     """Per-degree norms ||a_l||, ||b_l|| over band L (l = 0..L)."""
     keep = band_mask(idx, L)

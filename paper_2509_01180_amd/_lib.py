@@ -62,6 +62,7 @@ SIGNATURES = {
     "bh_plan_create": (_I, [_I, _I, _I, ctypes.POINTER(_P)]),
     "bh_plan_destroy": (None, [_P]),
     "bh_plan_num_coeffs": (_I64, [_P, _I]),
+    "bh_plan_check": (_I, [_P, _P]),
     "bh_expand": (_I, [_P, _P, _I64, _P, _P]),
     "bh_expand_ex": (_I, [_P, _P, _I64, _I, _P, _P, _P]),
     "bh_cross_power": (_I, [_P, _P, _P, _I64, _I, _P, _P]),
@@ -69,6 +70,7 @@ SIGNATURES = {
     "bh_align": (_I, [_P, _P, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),
     "bh_correlate_hess": (_I, [_P, _P, _P, _I64, _I, _P, _I, _P, _P, _P, _P]),
     "bh_degree_energy": (_I, [_P, _P, _P, _I64, _I, _P, _P]),
+    "bh_select_bands": (_I, [_P, _P, _P, _I, _P, _I64, _I, _pF64, _I, _P, _P, _P, _P]),
     "bh_prune_candidates": (_I, [_P, _P, _P, _I64, _I, _I, ctypes.c_double, _P, _P, _P]),
     "bh_align_shifts": (_I, [_P, _P, _I64, _P, _I, _P, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P]),
     "bh_expand_into": (_I, [_P, _P, _I64, _I, _P, _I64, _P, _P]),

@@ -114,6 +114,12 @@ class Plan:
     def __exit__(self, *exc):
         self.close()
 
+    def check(self) -> None:
+        """Synchronise the current stream and raise BhError (BH_EINVAL) if a
+        kernel of this plan met a template index outside its table since the
+        last check (see bh_plan_check)."""
+        check(lib().bh_plan_check(self._h, _stream()), "bh_plan_check")
+
     def num_coeffs(self, L: int) -> int:
         return check(lib().bh_plan_num_coeffs(self._h, int(L)), "bh_plan_num_coeffs")
 
@@ -333,6 +339,47 @@ class Plan:
         check(lib().bh_degree_energy(self._h, _ptr(a), _ptr(b), B, int(L), _ptr(out), _stream()),
               "bh_degree_energy")
         return out
+
+    def select_bands(self, a: torch.Tensor, templates: torch.Tensor,
+                     tmpl_idx: torch.Tensor | None, L_top: int, thresholds: Sequence[float],
+                     ratio: bool = False, out: tuple | None = None):
+        """Energy-ratio band selection (see bh_select_bands).
+
+        templates: [T, C, 2] float32 (or [C, 2] for one template); tmpl_idx:
+        [B] int32 (None if T == 1).  Returns (bands [B, n_tau] int32, common
+        [n_tau] int32, ratio [B, L_top + 1] float64 or None), all on the
+        device; out: optional (bands, common) buffers to fill."""
+        import numpy as np
+        B = a.shape[0]
+        if templates.dim() == 2:
+            templates = templates.unsqueeze(0)
+        T = templates.shape[0]
+        _dev(a, torch.float32, (B, self.C, 2), "a")
+        _dev(templates, torch.float32, (T, self.C, 2), "templates")
+        if tmpl_idx is not None:
+            _dev(tmpl_idx, torch.int32, (B,), "tmpl_idx")
+        th = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float64).reshape(-1))
+        n = len(th)
+        if out is None:
+            bands = torch.empty((B, n), dtype=torch.int32, device=a.device)
+            common = torch.empty((n,), dtype=torch.int32, device=a.device)
+        else:
+            bands, common = out
+            _dev(bands, torch.int32, (B, n), "bands")
+            _dev(common, torch.int32, (n,), "common")
+        r = (torch.empty((B, int(L_top) + 1), dtype=torch.float64, device=a.device)
+             if ratio else None)
+        check(lib().bh_select_bands(self._h, _ptr(a), _ptr(templates), T, _ptr(tmpl_idx), B,
+                                    int(L_top), _f64(th), n, _ptr(bands), _ptr(common), _ptr(r),
+                                    _stream()), "bh_select_bands")
+        return bands, common, r
+
+    @staticmethod
+    def schedule(common, L_top: int) -> list:
+        """March schedule from the batch choices of select_bands: the
+        distinct choices above 0, increasing, then L_top."""
+        vals = sorted({int(x) for x in common} - {0} - {int(L_top)})
+        return vals + [int(L_top)]
 
     def align(self, a: torch.Tensor, b: torch.Tensor, bands: Sequence[int], starts: torch.Tensor,
               steps: int, step_init: float = 1.0, step_grow: float = 1.25,

@@ -155,6 +155,17 @@ int get_band(bh_plan* p, int L, const DevBand** out) {
   return BH_OK;
 }
 
+// BH_EINVAL (and the flag cleared) if a kernel of an earlier call on this
+// plan met a template index outside its table.
+int take_pending_error(bh_plan* p) {
+  if (p->err_host && __atomic_exchange_n(p->err_host, 0, __ATOMIC_ACQ_REL) != 0)
+    return set_error(BH_EINVAL,
+                     "an earlier call on this plan had a template index outside "
+                     "0..n_templates-1; the scores, step scales and energies of those particles "
+                     "are NaN");
+  return BH_OK;
+}
+
 }  // namespace bh
 
 using namespace bh;
@@ -241,6 +252,14 @@ int bh_plan_create(int N, int L_max, int device, bh_plan** out) {
     p->N = N;
     p->L_max = L_max;
     p->device = device;
+    if (hipHostMalloc((void**)&p->err_host, sizeof(int),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+      p->err_host = nullptr;
+      (void)hipGetLastError();
+      return set_error(BH_ENOMEM, "pinned error word allocation failed");
+    }
+    *p->err_host = 0;
+    BH_HIP(hipHostGetDevicePointer((void**)&p->err_dev, p->err_host, 0));
     p->idx = &index_set(L_max);
     for (int L = 0; L <= L_max; ++L) p->band_size.push_back(index_set(L).C);
     int rc = build_basis(p.get());
@@ -258,11 +277,22 @@ void bh_plan_destroy(bh_plan* p) {
                   (void*)p->csgn})
     if (q) (void)hipFree(q);
   for (Buffer* b : {&p->gathered, &p->partial, &p->xi_scr, &p->state_scr, &p->misc_scr,
-                    &p->prune_scr, &p->shift_scr, &p->newton_scr})
+                    &p->prune_scr, &p->shift_scr, &p->newton_scr, &p->energy_scr})
     if (b->ptr) (void)hipFree(b->ptr);
   for (auto& kv : p->bands) free_band(kv.second);
+  if (p->err_host) (void)hipHostFree(p->err_host);
   p->prof.destroy();
   delete p;
+}
+
+int bh_plan_check(bh_plan* p, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    BH_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return take_pending_error(p);
+  });
 }
 
 int bh_plan_autotune(bh_plan* p, int64_t B, int n_restarts, const int32_t* bands, int n_bands,
@@ -489,6 +519,40 @@ int bh_degree_energy(bh_plan* p, const float* a, const float* b, int64_t B, int 
   });
 }
 
+int bh_select_bands(bh_plan* p, const float* a, const float* templates, int n_templates,
+                    const int32_t* tmpl_idx, int64_t B, int L_top, const double* thresholds,
+                    int n_tau, int32_t* bands, int32_t* common, double* ratio, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (L_top < 0 || L_top > p->L_max) return set_error(BH_EINVAL, "L_top outside 0..L_max");
+  if (B < 0 || B > (1LL << 24)) return set_error(BH_EINVAL, "batch size out of range");
+  if (n_templates < 1 || n_templates > (1 << 20)) return set_error(BH_EINVAL, "bad template count");
+  if (n_templates > 1 && !tmpl_idx) return set_error(BH_EINVAL, "template index table is NULL");
+  if (n_tau < 1 || n_tau > kMaxBandThresholds || !thresholds)
+    return set_error(BH_EINVAL, "threshold count outside 1..16");
+  BandThresholds th = {};
+  for (int j = 0; j < n_tau; ++j) {
+    if (!(thresholds[j] >= 0.0 && thresholds[j] <= 1.0))
+      return set_error(BH_EINVAL, "thresholds must lie in [0, 1]");
+    th.t[j] = thresholds[j];
+  }
+  int rc = take_pending_error(p);
+  if (rc != BH_OK) return rc;
+  if (B == 0) return BH_OK;
+  if (!a || !templates || !bands) return set_error(BH_EINVAL, "NULL buffer");
+  if (!pairs_aligned(a) || !pairs_aligned(templates))
+    return set_error(BH_EINVAL, "coefficient buffer not 8-byte aligned");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    const DevBand* band = nullptr;
+    int rc2 = get_band(p, L_top, &band);
+    if (rc2 != BH_OK) return rc2;
+    return launch_select_bands(p, *band, a, templates, n_templates > 1 ? tmpl_idx : nullptr,
+                               n_templates, B, th, n_tau, bands, common, ratio,
+                               (hipStream_t)stream);
+  });
+}
+
 static int check_align_opts(const bh_plan* p, const bh_align_opts* o) {
   if (o->n_bands < 1 || o->n_bands > 16 || !o->bands) return set_error(BH_EINVAL, "bad band list");
   for (int i = 0; i < o->n_bands; ++i)
@@ -519,6 +583,7 @@ int bh_align_t(bh_plan* p, const float* a, const float* templates, int n_templat
   if (n_templates > 1 && !tmpl_idx) return set_error(BH_EINVAL, "template index table is NULL");
   int rc = check_align_opts(p, o);
   if (rc != BH_OK) return rc;
+  if ((rc = take_pending_error(p)) != BH_OK) return rc;
   if (B == 0) return BH_OK;
   if (!a || !templates || !starts || !euler_out || !score_out) return set_error(BH_EINVAL, "NULL buffer");
   if (!pairs_aligned(a) || !pairs_aligned(templates))
@@ -566,6 +631,7 @@ int bh_align_uneven(bh_plan* p, const float* a, int64_t lda, const int32_t* Lp,
   if (n_templates > 1 && !tmpl_idx) return set_error(BH_EINVAL, "template index table is NULL");
   int rc = check_align_opts(p, o);
   if (rc != BH_OK) return rc;
+  if ((rc = take_pending_error(p)) != BH_OK) return rc;
   if (B == 0) return BH_OK;
   if (!a || !Lp || !templates || !starts || !euler_out || !score_out)
     return set_error(BH_EINVAL, "NULL buffer");

@@ -157,8 +157,13 @@ struct bh_plan {
   int32_t* csrc = nullptr;       // [C][2] real column feeding re/im of each complex coefficient
   float* csgn = nullptr;         // [C][2] sign applied to it
   std::vector<int64_t> band_size;   // C(L) for L = 0..L_max
+  // error word raised by kernels that meet a template index outside the
+  // table: pinned, mapped host memory (err_host) and its device address
+  int* err_host = nullptr;
+  int* err_dev = nullptr;
   // scratch (grown on demand, owned by the plan)
-  bh::Buffer gathered, partial, xi_scr, state_scr, misc_scr, prune_scr, shift_scr, newton_scr;
+  bh::Buffer gathered, partial, xi_scr, state_scr, misc_scr, prune_scr, shift_scr, newton_scr,
+      energy_scr;
   std::map<int, bh::DevBand> bands;
   bh::Profiler prof;
   // autotuned launch shapes (0 / absent: the built-in rules)
@@ -261,6 +266,14 @@ int time_on_stream(hipStream_t s, int reps, Prep&& prepare, Launch&& launch, flo
 int tune_march(bh_plan* p, int64_t B, int P, const int32_t* bands, int n_bands, hipStream_t s);
 int tune_expand_f32(bh_plan* p, int64_t B, hipStream_t s);
 int tune_expand_bf16(bh_plan* p, int64_t B, hipStream_t s);
+// Thresholds of the energy-ratio band selection, passed by value.
+constexpr int kMaxBandThresholds = 16;
+struct BandThresholds {
+  double t[kMaxBandThresholds];
+};
+int launch_select_bands(bh_plan* p, const DevBand& band, const float* a, const float* templates,
+                        const int32_t* tmpl, int n_tmpl, int64_t B, const BandThresholds& th,
+                        int n_tau, int32_t* bands, int32_t* common, double* ratio, hipStream_t s);
 int launch_prune(bh_plan* p, const double* euler, const double* score, int64_t B, int P, int K,
                  double min_sep, double* euler_out, double* score_out, hipStream_t s);
 int launch_align_shifts(bh_plan* p, const float* vols, int64_t B, const int32_t* shifts_host,

@@ -89,11 +89,18 @@ __global__ void k_xi_dense(const float* __restrict__ a, const float* __restrict_
   xi[(pb * E + t) * 2 + 1] = sim;
 }
 
-// Template of particle pb: tmpl[pb] clamped to [0, n_tmpl) (template 0 without a table).
+// Template of particle pb (template 0 without a table), or -1 when tmpl[pb]
+// lies outside [0, n_tmpl).  For such a particle the kernels read template 0
+// in its place (no access outside the table), write NaN results and raise
+// the plan's error word `bad` (a mapped host word; any writer stores 1).
 __device__ inline int64_t template_of(const int32_t* __restrict__ tmpl, int n_tmpl, int64_t pb) {
   if (!tmpl) return 0;
   const int t = tmpl[pb];
-  return t < 0 ? 0 : (t >= n_tmpl ? n_tmpl - 1 : t);
+  return (t < 0 || t >= n_tmpl) ? -1 : t;
+}
+
+__device__ inline void raise_bad(int* bad) {
+  if (bad) *reinterpret_cast<volatile int*>(bad) = 1;
 }
 
 // Class-major weighted cross-power of one band: X[pb][e] = {X1re, X1im, X2re, X2im}.
@@ -102,14 +109,17 @@ __global__ void k_xi_classes(const float* __restrict__ a, int64_t lda,
                              const int32_t* __restrict__ tmpl, int n_tmpl,
                              int64_t n_entries, const int32_t* __restrict__ sel,
                              const double* __restrict__ wt, const int32_t* __restrict__ deg_start,
-                             const int32_t* __restrict__ deg_off, double* __restrict__ X) {
+                             const int32_t* __restrict__ deg_off, double* __restrict__ X,
+                             int* bad) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t pb = blockIdx.y;
   if (e >= n_entries) return;
+  const int64_t ti = template_of(tmpl, n_tmpl, pb);
+  if (ti < 0 && e == 0) raise_bad(bad);
   const int l = sel[4 * e], m = sel[4 * e + 1], n = sel[4 * e + 2];
   const double w1 = wt[2 * e], w2 = wt[2 * e + 1];
   const float2* ap = reinterpret_cast<const float2*>(a + pb * 2 * lda);
-  const float2* b = reinterpret_cast<const float2*>(btab + template_of(tmpl, n_tmpl, pb) * 2 * ldt);
+  const float2* b = reinterpret_cast<const float2*>(btab + (ti < 0 ? 0 : ti) * 2 * ldt);
   double x1r = 0, x1i = 0, x2r = 0, x2i = 0;
   for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
     const int o = deg_off[i];
@@ -122,10 +132,11 @@ __global__ void k_xi_classes(const float* __restrict__ a, int64_t lda,
     x2i += bnr * ami - bni * amr;
   }
   double* out = X + (pb * n_entries + e) * 4;
-  out[0] = w1 * x1r;
-  out[1] = w1 * x1i;
-  out[2] = w2 * x2r;
-  out[3] = w2 * x2i;
+  const double nan = __builtin_nan("");
+  out[0] = ti < 0 ? nan : w1 * x1r;
+  out[1] = ti < 0 ? nan : w1 * x1i;
+  out[2] = ti < 0 ? nan : w2 * x2r;
+  out[3] = ti < 0 ? nan : w2 * x2i;
 }
 
 // W_b = sum_l l(l+1) ||a_l|| ||b_l|| over the band; one block per particle.
@@ -133,11 +144,13 @@ __global__ void k_band_weight(const float* __restrict__ a, int64_t lda,
                               const float* __restrict__ btab, int64_t ldt,
                               const int32_t* __restrict__ tmpl, int n_tmpl,
                               int L, const int32_t* __restrict__ deg_start,
-                              const int32_t* __restrict__ deg_off, double* __restrict__ Wb) {
+                              const int32_t* __restrict__ deg_off, double* __restrict__ Wb,
+                              int* bad) {
   __shared__ double part[BH_MAX_L + 1];
   const int64_t pb = blockIdx.x;
+  const int64_t ti = template_of(tmpl, n_tmpl, pb);
   const float* ap = a + pb * 2 * lda;
-  const float* b = btab + template_of(tmpl, n_tmpl, pb) * 2 * ldt;
+  const float* b = btab + (ti < 0 ? 0 : ti) * 2 * ldt;
   for (int l = threadIdx.x; l <= L; l += blockDim.x) {
     double na = 0.0, nb = 0.0;
     for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
@@ -155,7 +168,8 @@ __global__ void k_band_weight(const float* __restrict__ a, int64_t lda,
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int l = 0; l <= L; ++l) s += part[l];
-    Wb[pb] = s;
+    Wb[pb] = ti < 0 ? __builtin_nan("") : s;
+    if (ti < 0) raise_bad(bad);
   }
 }
 
@@ -170,13 +184,15 @@ __global__ __launch_bounds__(512) void k_xi_band(
     const int32_t* __restrict__ tmpl, int n_tmpl, int64_t n_entries,
     const int32_t* __restrict__ sel, const double* __restrict__ wt,
     const int32_t* __restrict__ deg_start, const int32_t* __restrict__ deg_off, int L, int CL,
-    double* __restrict__ X, double* __restrict__ Wb) {
+    double* __restrict__ X, double* __restrict__ Wb, int* bad) {
   extern __shared__ float2 sa[];   // [CL]
   __shared__ double part[BH_MAX_L + 1];
   const int tid = threadIdx.x;
   const int64_t pb = blockIdx.x;
+  const int64_t ti = template_of(tmpl, n_tmpl, pb);
+  const double nan = __builtin_nan("");
   const float2* ap = reinterpret_cast<const float2*>(a + pb * 2 * lda);
-  const float2* b = reinterpret_cast<const float2*>(btab + template_of(tmpl, n_tmpl, pb) * 2 * ldt);
+  const float2* b = reinterpret_cast<const float2*>(btab + (ti < 0 ? 0 : ti) * 2 * ldt);
   for (int i = tid; i < CL; i += blockDim.x) sa[i] = ap[i];
   __syncthreads();
   double* Xp = X + pb * n_entries * 4;
@@ -195,10 +211,10 @@ __global__ __launch_bounds__(512) void k_xi_band(
       x2i += bnr * ami - bni * amr;
     }
     double* out = Xp + e * 4;
-    out[0] = w1 * x1r;
-    out[1] = w1 * x1i;
-    out[2] = w2 * x2r;
-    out[3] = w2 * x2i;
+    out[0] = ti < 0 ? nan : w1 * x1r;
+    out[1] = ti < 0 ? nan : w1 * x1i;
+    out[2] = ti < 0 ? nan : w2 * x2r;
+    out[3] = ti < 0 ? nan : w2 * x2i;
   }
   for (int l = tid; l <= L; l += blockDim.x) {
     double na = 0.0, nb = 0.0;
@@ -217,7 +233,8 @@ __global__ __launch_bounds__(512) void k_xi_band(
   if (tid == 0) {
     double w = 0.0;
     for (int l = 0; l <= L; ++l) w += part[l];
-    Wb[pb] = w;
+    Wb[pb] = ti < 0 ? nan : w;
+    if (ti < 0) raise_bad(bad);
   }
 }
 
@@ -733,11 +750,13 @@ __global__ __launch_bounds__(64) void k_prune(const double* __restrict__ state,
 __global__ __launch_bounds__(256) void k_degree_energy(
     const float* __restrict__ a, const float* __restrict__ btab, int64_t C,
     const int32_t* __restrict__ tmpl, int n_tmpl, int L, const int32_t* __restrict__ deg_start,
-    const int32_t* __restrict__ deg_off, double* __restrict__ energy) {
+    const int32_t* __restrict__ deg_off, double* __restrict__ energy, int* bad) {
   __shared__ double part[256];
   const int64_t pb = blockIdx.x;
+  const int64_t ti = template_of(tmpl, n_tmpl, pb);
+  if (ti < 0 && threadIdx.x == 0) raise_bad(bad);
   const float* ap = a + pb * 2 * C;
-  const float* b = btab + template_of(tmpl, n_tmpl, pb) * 2 * C;
+  const float* b = btab + (ti < 0 ? 0 : ti) * 2 * C;
   for (int l = 0; l <= L; ++l) {
     const int w = 2 * l + 1;
     double acc = 0.0;
@@ -759,8 +778,68 @@ __global__ __launch_bounds__(256) void k_degree_energy(
       if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
       __syncthreads();
     }
-    if (threadIdx.x == 0) energy[pb * (L + 1) + l] = part[0];
+    if (threadIdx.x == 0) energy[pb * (L + 1) + l] = ti < 0 ? __builtin_nan("") : part[0];
     __syncthreads();
+  }
+}
+
+// Energy ratio of each particle's band-L cross-power and, per threshold,
+// the smallest L' with Ratio(L') <= tau (one thread per particle):
+// Ratio(L') = sum_{l > L'} E_l / sum_l E_l, the tails summed from the top
+// degree down (no cancellation for small tails); 0 when every E_l is 0.  A
+// NaN energy (template index outside the table) gives NaN ratios and the
+// band L for every threshold.
+__global__ void k_select_bands(const double* __restrict__ energy, int64_t B, int L,
+                               BandThresholds th, int n_tau, int32_t* __restrict__ bands,
+                               double* __restrict__ ratio) {
+  const int64_t pb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pb >= B) return;
+  const double* E = energy + pb * (L + 1);
+  double tot = 0.0;
+  for (int l = L; l >= 0; --l) tot += E[l];
+  int32_t pick[kMaxBandThresholds];
+  for (int j = 0; j < n_tau; ++j) pick[j] = L;
+  // walk L' downwards: the last L' that satisfies a threshold is the smallest
+  double tail = 0.0;
+  for (int Lq = L; Lq >= 0; --Lq) {
+    const double r = tot == 0.0 ? 0.0 : tail / tot;
+    if (ratio) ratio[pb * (L + 1) + Lq] = r;
+    for (int j = 0; j < n_tau; ++j)
+      if (r <= th.t[j]) pick[j] = Lq;
+    tail += E[Lq];
+  }
+  for (int j = 0; j < n_tau; ++j) bands[pb * n_tau + j] = pick[j];
+}
+
+// Batch choice per threshold j: the smallest L' whose per-particle choices
+// are <= L' for at least ceil(B/2) particles (the lower median of the
+// choices; the same as the smallest L' whose ratio is <= tau for at least
+// half the particles, Ratio being non-increasing in L').  One block per
+// threshold, an integer histogram in LDS.
+__global__ __launch_bounds__(256) void k_common_bands(const int32_t* __restrict__ bands,
+                                                      int64_t B, int L, int n_tau,
+                                                      int32_t* __restrict__ common) {
+  __shared__ int64_t hist[BH_MAX_L + 1];
+  const int j = blockIdx.x;
+  for (int l = threadIdx.x; l <= L; l += blockDim.x) hist[l] = 0;
+  __syncthreads();
+  for (int64_t b = threadIdx.x; b < B; b += blockDim.x) {
+    const int v = bands[b * n_tau + j];
+    atomicAdd(reinterpret_cast<unsigned long long*>(&hist[v < 0 ? 0 : (v > L ? L : v)]), 1ull);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t need = (B + 1) / 2;
+    int64_t cum = 0;
+    int pick = L;
+    for (int l = 0; l <= L; ++l) {
+      cum += hist[l];
+      if (cum >= need) {
+        pick = l;
+        break;
+      }
+    }
+    common[j] = pick;
   }
 }
 
@@ -960,7 +1039,7 @@ int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b
     ProfScope ps(p, "xi_classes", s, B);
     hipLaunchKernelGGL(k_xi_band, dim3((unsigned)B), dim3(512), (size_t)CL * sizeof(float2), s, a,
                        lda, b, ldt, tmpl, n_tmpl, band.n_entries, band.sel, band.wt,
-                       band.deg_start, band.deg_off, band.L, (int)CL, *X, Wb);
+                       band.deg_start, band.deg_off, band.L, (int)CL, *X, Wb, p->err_dev);
     BH_HIP(hipGetLastError());
     return BH_OK;
   }
@@ -968,13 +1047,13 @@ int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b
     ProfScope ps(p, "xi_classes", s, B);
     hipLaunchKernelGGL(k_xi_classes, dim3((unsigned)((band.n_entries + 127) / 128), (unsigned)B),
                        dim3(128), 0, s, a, lda, b, ldt, tmpl, n_tmpl, band.n_entries, band.sel,
-                       band.wt, band.deg_start, band.deg_off, *X);
+                       band.wt, band.deg_start, band.deg_off, *X, p->err_dev);
   }
   BH_HIP(hipGetLastError());
   if (Wb) {
     ProfScope ps(p, "band_weight", s, B);
     hipLaunchKernelGGL(k_band_weight, dim3((unsigned)B), dim3(64), 0, s, a, lda, b, ldt, tmpl,
-                       n_tmpl, band.L, band.deg_start, band.deg_off, Wb);
+                       n_tmpl, band.L, band.deg_start, band.deg_off, Wb, p->err_dev);
     BH_HIP(hipGetLastError());
   }
   return BH_OK;
@@ -998,8 +1077,31 @@ int launch_degree_energy(bh_plan* p, const DevBand& band, const float* a, const 
                          hipStream_t s) {
   ProfScope ps(p, "degree_energy", s, B);
   hipLaunchKernelGGL(k_degree_energy, dim3((unsigned)B), dim3(256), 0, s, a, b, p->C, tmpl, n_tmpl,
-                     band.L, band.deg_start, band.deg_off, energy);
+                     band.L, band.deg_start, band.deg_off, energy, p->err_dev);
   BH_HIP(hipGetLastError());
+  return BH_OK;
+}
+
+int launch_select_bands(bh_plan* p, const DevBand& band, const float* a, const float* templates,
+                        const int32_t* tmpl, int n_tmpl, int64_t B, const BandThresholds& th,
+                        int n_tau, int32_t* bands, int32_t* common, double* ratio,
+                        hipStream_t s) {
+  const int L = band.L;
+  int rc = grow(p->energy_scr, (size_t)B * (L + 1) * sizeof(double));
+  if (rc != BH_OK) return rc;
+  double* E = (double*)p->energy_scr.ptr;
+  if ((rc = launch_degree_energy(p, band, a, templates, tmpl, n_tmpl, B, E, s)) != BH_OK) return rc;
+  {
+    ProfScope ps(p, "select_bands", s, B);
+    hipLaunchKernelGGL(k_select_bands, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, E, B, L,
+                       th, n_tau, bands, ratio);
+  }
+  BH_HIP(hipGetLastError());
+  if (common) {
+    hipLaunchKernelGGL(k_common_bands, dim3((unsigned)n_tau), dim3(256), 0, s, bands, B, L, n_tau,
+                       common);
+    BH_HIP(hipGetLastError());
+  }
   return BH_OK;
 }
 

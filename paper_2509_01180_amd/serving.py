@@ -76,12 +76,15 @@ class Request:
 
 @dataclass
 class Cohort:
+    """Requests admitted together for one box edge; `bands` is its march
+    schedule, the box's at admission."""
     box: int
     requests: list
     n: int
     nbytes: int
     tick: int
     cursor: int = 0                     # index of the next band to run
+    bands: tuple = ()
     dev: dict = field(default_factory=dict)
 
 
@@ -120,7 +123,8 @@ class Scheduler:
                 break
             self.queue.popleft()
             if c is None:
-                c = new[r.box] = Cohort(box=r.box, requests=[], n=0, nbytes=0, tick=self.ticks)
+                c = new[r.box] = Cohort(box=r.box, requests=[], n=0, nbytes=0, tick=self.ticks,
+                                        bands=self.specs[r.box].bands)
             c.requests.append(r)
             c.n += r.n
             c.nbytes += need
@@ -133,8 +137,7 @@ class Scheduler:
         """(cohort, band, is_last) for every live cohort, in admission order."""
         out = []
         for c in self.live:
-            bands = self.specs[c.box].bands
-            out.append((c, bands[c.cursor], c.cursor == len(bands) - 1))
+            out.append((c, c.bands[c.cursor], c.cursor == len(c.bands) - 1))
         return out
 
     def advance(self) -> list:
@@ -142,7 +145,7 @@ class Scheduler:
         done, keep = [], []
         for c in self.live:
             c.cursor += 1
-            if c.cursor == len(self.specs[c.box].bands):
+            if c.cursor == len(c.bands):
                 done.append(c)
                 self.used -= c.nbytes
             else:
@@ -178,15 +181,27 @@ class Engine:
                  budget_bytes: int = 24 << 30, max_cohort: int = 2048, device: int = 0,
                  step_init: float = 1.0, step_grow: float = 1.25, step_shrink: float = 0.5,
                  plans: dict | None = None, method: str = "march", keep: int = 8,
-                 min_sep: float = 0.17453292519943295, newton_steps: int = 6):
+                 min_sep: float = 0.17453292519943295, newton_steps: int = 6,
+                 band_thresholds: Sequence[float] | None = None):
         """method "march": gradient steps on every band; "paper": after the
         first band only `keep` candidates (local maxima at least `min_sep`
-        radians apart) continue, with `newton_steps` Newton steps per band."""
+        radians apart) continue, with `newton_steps` Newton steps per band.
+
+        band_thresholds: choose each box edge's march schedule by the
+        energy ratio (bh_select_bands, Fig. 1 caption and Sec. III) instead
+        of the given bands: each resident template's cross-power with
+        itself up to the box's largest band, the batch choice over the
+        templates for these thresholds, then that band.  It is chosen once,
+        here, from the templates only, so a request's result still does not
+        depend on the requests it is served with (a choice per cohort from
+        the particles would)."""
         import torch
         from .api import Plan
         if method not in ("march", "paper"):
             raise ValueError("method is 'march' or 'paper'")
         self.method, self.keep, self.min_sep = method, int(keep), float(min_sep)
+        self.band_thresholds = (None if band_thresholds is None
+                                else tuple(float(t) for t in band_thresholds))
         self.newton_steps = int(newton_steps)
         self.torch = torch
         self.dev = torch.device("cuda", device)
@@ -212,6 +227,21 @@ class Engine:
             if t.dtype != torch.float32 or t.dim() != 3 or t.shape[1:] != (self.plans[N].C, 2):
                 raise ValueError(f"templates of {N}^3 must be [T, {self.plans[N].C}, 2] float32")
             self.templates[N] = t.contiguous()
+        # the templates may still be in flight on the caller's stream
+        cur = torch.cuda.current_stream(self.dev)
+        for N, s in self.streams.items():
+            s.wait_stream(cur)
+            if N in self.templates:
+                self.templates[N].record_stream(s)
+        if self.band_thresholds is not None:
+            for N, spec in specs.items():
+                if N not in self.templates:
+                    continue
+                t = self.templates[N]
+                ti = torch.arange(t.shape[0], dtype=torch.int32, device=self.dev)
+                L_top = max(spec.bands)
+                _b, common, _r = self.plans[N].select_bands(t, t, ti, L_top, self.band_thresholds)
+                spec.bands = tuple(self.plans[N].schedule(common.cpu().tolist(), L_top))
         self.sched = Scheduler(specs, budget_bytes, max_cohort)
         self.pending: list = []              # finished cohorts awaiting their event
         self.ticks_in_flight: deque = deque()
@@ -294,6 +324,10 @@ class Engine:
     def _start(self, c: Cohort) -> None:
         torch = self.torch
         plan, s = self.plans[c.box], self.streams[c.box]
+        # tensors handed in with a request were produced on the caller's
+        # stream: the box stream waits for it before reading them, and they
+        # are marked as used on the box stream for the caching allocator
+        s.wait_stream(torch.cuda.current_stream(self.dev))
         with torch.cuda.stream(s):
             vols = [r.volumes() if callable(r.volumes) else r.volumes for r in c.requests]
             starts = [r.starts() if callable(r.starts) else r.starts for r in c.requests]
@@ -302,6 +336,8 @@ class Engine:
                     raise ValueError(f"request {r.rid}: volumes must be [{r.n}, {c.box}^3] float32")
                 if tuple(st.shape) != (r.n, self.P, 3) or st.dtype != torch.float64:
                     raise ValueError(f"request {r.rid}: starts must be [{r.n}, {self.P}, 3] float64")
+                v.record_stream(s)
+                st.record_stream(s)
             v = vols[0].contiguous() if len(vols) == 1 else torch.cat(vols)
             d = c.dev
             d["a"] = torch.empty((c.n, plan.C, 2), dtype=torch.float32, device=self.dev)
@@ -315,6 +351,7 @@ class Engine:
             d["score"] = torch.empty((c.n,), dtype=torch.float64, device=self.dev)
             if self.method == "paper":
                 d["all_score"] = torch.empty((c.n, self.P), dtype=torch.float64, device=self.dev)
+
 
     def _band(self, c: Cohort, band: int, last: bool) -> None:
         torch = self.torch

@@ -74,6 +74,68 @@ def test_degree_energy_vs_oracle():
     plan.close()
 
 
+def test_select_bands_vs_oracle():
+    """Energy-ratio band selection (Fig. 1 caption, Sec. III) through
+    bh_select_bands: workload particles of two templates, the oracle's
+    expansion rounded to FP32 on both sides.  Per-particle ratios within
+    1e-12, the chosen bands identical (a ratio within 1e-9 of a threshold
+    would be a tie: either neighbouring band is then accepted), and the
+    batch choice equal to the oracle's count over particles."""
+    import torch
+    from paper_2509_01180_amd._lib import BhError
+    from paper_2509_01180_amd.api import Plan
+    dev = cuda_device()
+    w = synth.CONFIG1
+    N, Lmax = w.N, 16
+    idx = basis.IndexSet(Lmax)
+    rng = np.random.default_rng(51)
+    t2 = synth.render_blobs(synth.blob_template(rng, 30), N).astype(np.float32)
+    vols = np.stack([w.template_volume(), t2] + [w.particle(20 + i) for i in range(7)])
+    C = as_fp32_complex(expand.expand(vols.astype(np.float64), idx))
+    tmpl_c, A = C[:2], C[2:]
+    tid = np.array([0, 1, 0, 0, 1, 0, 1], dtype=np.int32)
+    taus = (0.3, 0.05, 0.01, 0.001)
+    say(f"select_bands N={N} Lmax={Lmax} B={len(A)} taus={taus}")
+    plan = Plan(N, Lmax, device=0)
+    da = torch.from_numpy(to_pairs(A)).to(dev).contiguous()
+    dt = torch.from_numpy(to_pairs(tmpl_c)).to(dev).contiguous()
+    ti = torch.from_numpy(tid).to(dev)
+    for L_top in (8, 16):
+        bands, common, ratio = plan.select_bands(da, dt, ti, L_top, taus, ratio=True)
+        plan.check()
+        bands, common, ratio = bands.cpu().numpy(), common.cpu().numpy(), ratio.cpu().numpy()
+        R = np.stack([score.energy_ratio(score.degree_energy(A[i], tmpl_c[tid[i]], idx, L_top))
+                      for i in range(len(A))])
+        np.testing.assert_allclose(ratio, R, rtol=0, atol=1e-12)
+        for i in range(len(A)):
+            for j, t in enumerate(taus):
+                ref = score.select_bands(R[i], [t])[0]
+                if bands[i, j] != ref:
+                    near = np.abs(R[i] - t) <= 1e-9
+                    assert near[min(bands[i, j], ref)], (i, t, bands[i, j], ref)
+        assert list(common) == score.select_bands_batch(R, taus)
+        print(f"L_top={L_top}: per particle {bands.tolist()}, batch {common.tolist()}, "
+              f"schedule {Plan.schedule(common, L_top)}")
+    # one template without an index table; limits of the thresholds
+    b1, c1, _r = plan.select_bands(da, dt[0], None, 12, (0.05,))
+    R0 = [score.energy_ratio(score.degree_energy(A[i], tmpl_c[0], idx, 12)) for i in range(len(A))]
+    assert list(c1.cpu().numpy()) == score.select_bands_batch(np.stack(R0), (0.05,))
+    for bad in ((), (1.5,), (-0.1,), tuple([0.1] * 17)):
+        with pytest.raises(BhError):
+            plan.select_bands(da, dt, ti, 8, bad)
+    with pytest.raises(BhError):
+        plan.select_bands(da, dt, ti, Lmax + 1, (0.1,))
+    # a template index outside the table: NaN ratios, L_top chosen, reported once
+    wild = torch.from_numpy(np.array([0, 1, 5, 0, 1, 0, -1], dtype=np.int32)).to(dev)
+    bw, _cw, rw = plan.select_bands(da, dt, wild, 8, (0.05,), ratio=True)
+    with pytest.raises(BhError):
+        plan.check()
+    rw, bw = rw.cpu().numpy(), bw.cpu().numpy()
+    assert np.all(np.isnan(rw[[2, 6]])) and np.all(bw[[2, 6]] == 8)
+    assert np.all(np.isfinite(rw[[0, 1, 3, 4, 5]]))
+    plan.close()
+
+
 def _workload(n, seed):
     w = synth.CONFIG1
     idx = basis.IndexSet(w.L_max)

@@ -67,12 +67,27 @@ def test_align_t_equals_single_template_align():
             rows = torch.from_numpy(np.nonzero(tid == t)[0]).to(dev)
             for x, y in zip(mix, one):
                 assert torch.equal(x[rows], y[rows])
-    # template indices outside the table are clamped to its ends
-    wild = torch.from_numpy(np.where(tid == 0, -3, np.where(tid == T_RES - 1, T_RES + 5, tid))
-                            .astype(np.int32)).to(dev)
+    # template indices outside the table: those particles score NaN, the
+    # others are untouched, and the plan reports BH_EINVAL once
+    from paper_2509_01180_amd import _lib
+    wild_np = np.where(tid == 0, -3, np.where(tid == T_RES - 1, T_RES + 5, tid)).astype(np.int32)
+    wild = torch.from_numpy(wild_np).to(dev)
     mix = plan.align_t(a, tmpl, ti, (5, 10), starts, STEPS, batch_invariant=True)
-    clamped = plan.align_t(a, tmpl, wild, (5, 10), starts, STEPS, batch_invariant=True)
-    assert torch.equal(mix[0], clamped[0]) and torch.equal(mix[1], clamped[1])
+    plan.check()
+    bad = plan.align_t(a, tmpl, wild, (5, 10), starts, STEPS, batch_invariant=True)
+    with pytest.raises(_lib.BhError) as ei:
+        plan.check()
+    assert ei.value.code == _lib.BH_EINVAL and b"template index" in _lib.lib().bh_last_error()
+    plan.check()   # reported once
+    ok = torch.from_numpy((wild_np >= 0) & (wild_np < T_RES)).to(dev)
+    assert torch.isnan(bad[1][~ok]).all()
+    assert torch.equal(mix[0][ok], bad[0][ok]) and torch.equal(mix[1][ok], bad[1][ok])
+    # a later align_t reports a flag raised by a completed call, at entry
+    plan.align_t(a, tmpl, wild, (5, 10), starts, STEPS, batch_invariant=True)
+    torch.cuda.synchronize()
+    with pytest.raises(_lib.BhError):
+        plan.align_t(a, tmpl, ti, (5, 10), starts, STEPS, batch_invariant=True)
+    plan.check()
     # a one-entry table with no index is the one-template case
     e1 = plan.align_t(a, tmpl[:1].contiguous(), None, (5, 10), starts, STEPS)
     e2 = plan.align(a, tmpl[0].contiguous(), (5, 10), starts, STEPS)
@@ -262,3 +277,36 @@ def test_paper_method_same_alone_and_in_mix():
         np.testing.assert_array_equal(a.score, r.score)
     for p in plans.values():
         p.close()
+
+
+def test_engine_chooses_bands_by_energy_ratio():
+    """Engine(band_thresholds=...) picks each box edge's schedule in the
+    library (bh_select_bands over the resident templates, each against
+    itself): the oracle's energy ratios of the same template volumes give
+    the same schedule; the engine then serves with it."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd.serving import Engine, Request
+    from oracle import score
+    dev = cuda_device()
+    N, L = 24, 10
+    taus = (0.2, 0.05)
+    plan = Plan(N, L, device=0)
+    tmpl, blobs = _templates(plan, N)
+    say(f"engine band selection N={N} L={L} taus={taus}")
+    eng = Engine({N: (L, (4, 7, 10))}, {N: tmpl}, restarts=P, steps=STEPS, plans={N: plan},
+                 method="paper", keep=6, newton_steps=4, band_thresholds=taus)
+    got = eng.sched.specs[N].bands
+    idx = basis.IndexSet(L)
+    tv = np.stack([synth.render_blobs(b, N) for b in blobs]).astype(np.float32)
+    C = expand.expand(tv.astype(np.float64), idx)
+    R = np.stack([score.energy_ratio(score.degree_energy(c, c, idx, L)) for c in C])
+    want = Plan.schedule(score.select_bands_batch(R, taus), L)
+    print(f"schedule {got} (oracle {want}); ratios {np.round(np.median(R, axis=0), 4)}")
+    assert list(got) == want
+    v, _g = _particles(blobs, N, 1, 3, 93)
+    r = eng.submit(Request(box=N, template=1, n=3, volumes=torch.from_numpy(v).to(dev),
+                           starts=torch.from_numpy(synth.serving.start_pool(3, P, 93)).to(dev)))
+    eng.drain()
+    assert np.all(np.isfinite(r.score))
+    plan.close()

@@ -60,6 +60,8 @@ MUTATIONS = [
      "tail = tot - np.cumsum(E)", "tail = tot - np.cumsum(E) + E"),
     ("band selection strict", "score.py",
      "hit = np.nonzero(r <= tau)[0]", "hit = np.nonzero(r < tau)[0]"),
+    ("batch band at the upper half", "score.py",
+     "need = (B + 1) // 2", "need = B // 2"),
     ("D with +i m alpha", "wigner.py",
      "np.exp(-1j * m * alpha)[:, None]", "np.exp(1j * m * alpha)[:, None]"),
     ("J_y sign", "wigner.py",

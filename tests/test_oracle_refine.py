@@ -93,6 +93,33 @@ def test_energy_ratio_and_band_selection():
     assert np.all(score.energy_ratio(np.zeros(4)) == 0)
 
 
+def test_batch_band_selection():
+    """The batch's band per threshold: at least half the particles' ratio
+    curves at or below tau.  Pinned by hand on made-up curves, by the
+    median formulation (for an odd batch the band of the median ratio
+    curve, taken pointwise in L) and by the lower median of the
+    per-particle choices."""
+    r = np.array([[0.5, 0.2, 0.05, 0.0],
+                  [0.6, 0.4, 0.1, 0.0],
+                  [0.3, 0.1, 0.01, 0.0]])
+    # tau 0.1: per-particle choices 2, 2, 1 -> at L=1 one curve of three is <= 0.1, at L=2 all
+    assert score.select_bands_batch(r, [0.1]) == [2]
+    # tau 0.2: choices 1, 2, 1 -> L=1; tau 0: every curve reaches 0 at L=3; tau 1: L=0
+    assert score.select_bands_batch(r, [0.2, 0.0, 1.0]) == [1, 3, 0]
+    rng = np.random.default_rng(3)
+    for B in (1, 5, 7, 8, 20):
+        E = rng.exponential(size=(B, 13)) * np.exp(-0.4 * np.arange(13))
+        R = np.stack([score.energy_ratio(e) for e in E])
+        taus = [0.3, 0.05, 0.01, 0.001]
+        got = score.select_bands_batch(R, taus)
+        per = np.array([[score.select_bands(R[b], [t])[0] for t in taus] for b in range(B)])
+        lower_median = np.sort(per, axis=0)[(B - 1) // 2]
+        assert got == list(lower_median)
+        if B % 2:
+            med = np.median(R, axis=0)
+            assert got == [score.select_bands(med, [t])[0] for t in taus]
+
+
 def test_prune_candidates_rules():
     # rotations about z by these angles (degrees): separations are exact
     ang = np.radians([0.0, 3.0, 40.0, 41.0, 90.0, 200.0])
