@@ -154,6 +154,30 @@ int bh_expand_into(bh_plan* p, const float* vols, int64_t B, int mode, float* co
                    float* coarse, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Allocation-free expansion, for callers that cannot allocate device memory
+ * during the call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same layouts as bh_expand; the result
+ * is bit-identical to bh_expand_ex with BH_EXPAND_FP32 |
+ * BH_EXPAND_BATCH_INVARIANT.
+ *
+ * Instead of the plan's growable scratch, the folded volumes and split-K
+ * partial sums live in one static device array of BH_NOALLOC_SCRATCH_BYTES
+ * per GPU, held by the library from its load until the process ends.  The
+ * batch is processed in passes of bh_expand_noalloc_batch(p) particles (a
+ * multiple of 128); a plan whose 128-particle pass does not fit (0 from
+ * bh_expand_noalloc_batch, e.g. box edges far above 96 at L = 40) gets
+ * BH_EUNSUPPORTED.  The call makes no hipMalloc, hipFree or other
+ * allocating call; the caller passes the volumes and the coefficient
+ * output.  All calls on one GPU share its scratch, so two calls that
+ * overlap on the device (different streams, or different host threads)
+ * race and give wrong results: serialise them.
+ * ------------------------------------------------------------------- */
+#define BH_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int bh_expand_noalloc(bh_plan* p, const float* vols, int64_t B, float* coeffs, void* stream);
+/* Particles per pass of bh_expand_noalloc for this plan; <0 on error. */
+int64_t bh_expand_noalloc_batch(const bh_plan* p);
+
+/* ---------------------------------------------------------------------
  * Cross-power of Eq. (2) for band L (0 <= L <= L_max).
  * a:  dev float[B][C(L_max)][2]  particle coefficients
  * b:  dev float[C(L_max)][2]     template coefficients

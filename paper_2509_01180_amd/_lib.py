@@ -65,6 +65,8 @@ SIGNATURES = {
     "bh_plan_check": (_I, [_P, _P]),
     "bh_expand": (_I, [_P, _P, _I64, _P, _P]),
     "bh_expand_ex": (_I, [_P, _P, _I64, _I, _P, _P, _P]),
+    "bh_expand_noalloc": (_I, [_P, _P, _I64, _P, _P]),
+    "bh_expand_noalloc_batch": (_I64, [_P]),
     "bh_cross_power": (_I, [_P, _P, _P, _I64, _I, _P, _P]),
     "bh_correlate": (_I, [_P, _P, _P, _I64, _I, _P, _I, _P, _P, _P]),
     "bh_align": (_I, [_P, _P, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),

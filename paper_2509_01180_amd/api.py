@@ -208,6 +208,21 @@ class Plan:
                                  _stream()), "bh_expand_ex")
         return out
 
+    def expand_noalloc(self, vols: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """bh_expand_noalloc: the batch-invariant FP32 expansion with the
+        library's static device scratch (no device allocation in the call).
+        `out` [B, C(L_max), 2] float32 is supplied by the caller."""
+        B = vols.shape[0]
+        _dev(vols, torch.float32, (B, self.N, self.N, self.N), "vols")
+        _dev(out, torch.float32, (B, self.C, 2), "out")
+        check(lib().bh_expand_noalloc(self._h, _ptr(vols), B, _ptr(out), _stream()),
+              "bh_expand_noalloc")
+        return out
+
+    def noalloc_batch(self) -> int:
+        """Particles per pass of expand_noalloc (0: the plan does not fit)."""
+        return check(lib().bh_expand_noalloc_batch(self._h), "bh_expand_noalloc_batch")
+
     def expand_into(self, vols: torch.Tensor, out: torch.Tensor, mode: str = "fp32",
                     coarse: torch.Tensor | None = None, batch_invariant: bool = False):
         """Expansion into rows of a wider coefficient array: out [B, ldc, 2]

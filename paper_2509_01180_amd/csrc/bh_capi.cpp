@@ -247,6 +247,8 @@ int bh_plan_create(int N, int L_max, int device, bh_plan** out) {
     if (device < 0 || device >= ndev) return set_error(BH_EINVAL, "device index out of range");
     DeviceGuard g(device);
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    int rc = noalloc_scratch_init(device);
+    if (rc != BH_OK) return rc;
     // owned here until it is complete (an exception or error frees it)
     std::unique_ptr<bh_plan, void (*)(bh_plan*)> p(new bh_plan(), bh_plan_destroy);
     p->N = N;
@@ -262,7 +264,7 @@ int bh_plan_create(int N, int L_max, int device, bh_plan** out) {
     BH_HIP(hipHostGetDevicePointer((void**)&p->err_dev, p->err_host, 0));
     p->idx = &index_set(L_max);
     for (int L = 0; L <= L_max; ++L) p->band_size.push_back(index_set(L).C);
-    int rc = build_basis(p.get());
+    rc = build_basis(p.get());
     if (rc != BH_OK) return rc;
     *out = p.release();
     return BH_OK;
@@ -401,6 +403,25 @@ int bh_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, void* str
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
     return launch_expand(p, vols, B, coeffs, (hipStream_t)stream);
   });
+}
+
+int bh_expand_noalloc(bh_plan* p, const float* vols, int64_t B, float* coeffs, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (B < 0 || B > (1LL << 21)) return set_error(BH_EINVAL, "batch size out of range");
+  if (B == 0) return BH_OK;
+  if (!vols || !coeffs) return set_error(BH_EINVAL, "NULL buffer");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    return launch_expand_noalloc(p, vols, B, coeffs, (hipStream_t)stream);
+  });
+}
+
+int64_t bh_expand_noalloc_batch(const bh_plan* p) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  int64_t tiles = 0;
+  noalloc_expand_pass(p, &tiles);
+  return tiles * kGemmBM;
 }
 
 int bh_expand_ex(bh_plan* p, const float* vols, int64_t B, int mode, float* coeffs, float* coarse,

@@ -17,6 +17,15 @@
 #include "bh_internal.h"
 
 #include <algorithm>
+#include <mutex>
+
+// Device scratch of the allocation-free expansion (bh_expand_noalloc): the
+// folded volumes and split-K partial sums of one pass.  Every GPU the
+// library runs on holds one copy for the life of the process.  Host code
+// never uses this name as an address: each device's copy is resolved once
+// with hipGetSymbolAddress (noalloc_scratch_init) and only that pointer is
+// handed to kernels.
+static __device__ __align__(256) float scratch[BH_NOALLOC_SCRATCH_BYTES / sizeof(float)];
 
 namespace bh {
 namespace {
@@ -258,6 +267,83 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
                      M_pad, p->C_pad, B, p->C, p->csrc, p->csgn, coeffs, ldc);
   }
   BH_HIP(hipGetLastError());
+  return BH_OK;
+}
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+int noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return set_error(BH_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return BH_OK;
+  int cur = -1;
+  BH_HIP(hipGetDevice(&cur));
+  if (cur != device) return set_error(BH_EDEVICE, "scratch lookup needs its device current");
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return set_error(BH_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                     hipGetErrorString(e));
+  }
+  g_scratch_ptr[device] = ptr;
+  return BH_OK;
+}
+
+int noalloc_expand_pass(const bh_plan* p, int64_t* tiles_per_pass) {
+  const int64_t nt = p->C_pad / BN, nk_total = p->VR_pad / BK;
+  const int nsplit = expand_split(1, nt, nk_total, true);
+  const size_t ft_tile = (size_t)kParityClasses * p->VR_pad * BM * sizeof(float);
+  const size_t part_tile = (size_t)nsplit * BM * p->C_pad * sizeof(float);
+  *tiles_per_pass = (int64_t)(BH_NOALLOC_SCRATCH_BYTES / (ft_tile + part_tile));
+  return nsplit;
+}
+
+// bh_expand_noalloc: the batch-invariant FP32 expansion (the same kernels,
+// split and summation order as launch_expand with batch_invariant) in passes
+// of whole 128-particle tiles whose folded volumes and partial sums fit the
+// static scratch.  Allocates nothing; the scratch needs no clearing (the
+// gather writes every folded value, padding included, and the GEMM every
+// partial sum before they are read).
+int launch_expand_noalloc(bh_plan* p, const float* vols, int64_t B, float* coeffs,
+                          hipStream_t s) {
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (p->device >= 0 && p->device < kMaxScratchDevices) base = g_scratch_ptr[p->device];
+  }
+  if (!base) return set_error(BH_EDEVICE, "scratch of this device not resolved");
+  int64_t tiles_per_pass = 0;
+  const int nsplit = noalloc_expand_pass(p, &tiles_per_pass);
+  if (tiles_per_pass < 1)
+    return set_error(BH_EUNSUPPORTED, "one 128-particle tile of this plan needs more than the " +
+                                          std::to_string(BH_NOALLOC_SCRATCH_BYTES >> 20) +
+                                          " MiB scratch");
+  const int64_t nt = p->C_pad / BN, nk = p->VR_pad / BK / nsplit;
+  const int64_t vol_stride = (int64_t)p->N * p->N * p->N;
+  for (int64_t b0 = 0; b0 < B; b0 += tiles_per_pass * BM) {
+    const int64_t nb = std::min(B - b0, tiles_per_pass * BM);
+    const int64_t M_pad = ((nb + BM - 1) / BM) * BM, mt = M_pad / BM;
+    float* Ft = (float*)base;
+    float* part = Ft + (size_t)kParityClasses * p->VR_pad * M_pad;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)(p->VR_pad / 32), (unsigned)(M_pad / 32)),
+                       dim3(256), 0, s, vols + b0 * vol_stride, vol_stride, nb, p->vrep, p->VR,
+                       p->VR_pad, M_pad, p->N, Ft);
+    BH_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)(mt * nt * nsplit)), dim3(256), 0, s, Ft,
+                       p->psi, part, M_pad, p->C_pad, p->VR_pad, p->ctiles, (int)nk, nsplit);
+    BH_HIP(hipGetLastError());
+    const int64_t tot = nb * p->C;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part,
+                       nsplit, M_pad, p->C_pad, nb, p->C, p->csrc, p->csgn,
+                       coeffs + 2 * b0 * p->C, p->C);
+    BH_HIP(hipGetLastError());
+  }
   return BH_OK;
 }
 

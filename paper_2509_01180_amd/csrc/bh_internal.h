@@ -221,6 +221,13 @@ struct ShiftTable {
 int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s,
                   bool batch_invariant = false, const ShiftTable* shifts = nullptr, int S = 1,
                   int64_t ldc = 0);
+// Allocation-free expansion: resolve this device's copy of the static
+// scratch (once per device, with the device current; called at plan
+// creation), how many 128-particle tiles one pass holds (returns the split-K
+// factor), and the launcher.
+int noalloc_scratch_init(int device);
+int noalloc_expand_pass(const bh_plan* p, int64_t* tiles_per_pass);
+int launch_expand_noalloc(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s);
 int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, float* coeffs,
                        float* coarse_out, hipStream_t s, bool batch_invariant = false,
                        int64_t ldc = 0);
