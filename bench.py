@@ -95,24 +95,62 @@ def make_inputs(w: synth.Workload, B: int, threads: int):
     return vols, starts
 
 
-def cpu_baseline(w: synth.Workload, n_particles: int):
-    """FP64 oracle (expansion + march) on the first particles of the workload."""
-    from oracle import align as oalign, basis, expand
+def _oracle_march_worker(job):
+    """One particle's FP64 oracle march (runs in a worker process, BLAS
+    limited to one thread)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import align as oalign, basis
+    a, b, L_max, bands, starts, steps = job
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        r = oalign.march(a, b, basis.IndexSet(L_max), bands, starts, steps)
+        return r["euler"][r["best"]], time.perf_counter() - t0
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w: synth.Workload, n_particles: int, workers: int):
+    """FP64 oracle on the first particles of the workload: one batched
+    expansion (template and particles, BLAS on one thread), then each
+    particle's march in a pool of worker processes (one BLAS thread each).
+    Returns wall time, CPU seconds (this process and its workers), the best
+    rotations, the oracle's coefficients and the phases' wall times."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from oracle import basis, expand
     idx = basis.IndexSet(w.L_max)
     tv = w.template_volume().astype(np.float64)
     vols = np.stack([w.particle(i) for i in range(n_particles)]).astype(np.float64)
-    r0 = resource.getrusage(resource.RUSAGE_SELF)
-    t0 = time.perf_counter()
-    b = expand.expand(tv, idx)
-    A = expand.expand(vols, idx)
-    out = []
-    for i in range(n_particles):
-        r = oalign.march(A[i], b, idx, w.bands, w.starts(i), w.steps)
-        out.append(r["euler"][r["best"]])
-    dt = time.perf_counter() - t0
-    r1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    return dt, cpu, np.array(out), A
+    starts = [w.starts(i) for i in range(n_particles)]
+    ctx = mp.get_context("spawn")   # a fresh interpreter per worker, nothing inherited
+    with ctx.Pool(workers) as pool:
+        pool.map(abs, range(workers))                 # workers started before the clock
+        r0s = resource.getrusage(resource.RUSAGE_SELF)
+        r0c = resource.getrusage(resource.RUSAGE_CHILDREN)
+        t0 = time.perf_counter()
+        with threadpool_limits(1):
+            c = expand.expand(np.concatenate([tv[None], vols]), idx)
+        t_exp = time.perf_counter() - t0
+        b, A = c[0], c[1:]
+        jobs = [(A[i], b, w.L_max, w.bands, starts[i], w.steps) for i in range(n_particles)]
+        out = pool.map(_oracle_march_worker, jobs, chunksize=1)
+        dt = time.perf_counter() - t0
+        r1s = resource.getrusage(resource.RUSAGE_SELF)
+        pool.close()
+        pool.join()
+    r1c = resource.getrusage(resource.RUSAGE_CHILDREN)
+    cpu = sum((x1.ru_utime - x0.ru_utime) + (x1.ru_stime - x0.ru_stime)
+              for x0, x1 in ((r0s, r1s), (r0c, r1c)))
+    march_s = [o[1] for o in out]
+    return dt, cpu, np.array([o[0] for o in out]), A, t_exp, march_s
 
 
 def geodesic_deg(e1, e2):
@@ -132,7 +170,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=None, help="particles per step (default 1000)")
-    ap.add_argument("--cpu-sample", type=int, default=1, help="particles timed on the oracle (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=8, help="particles timed on the oracle (0: skip)")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle worker processes (0: one per particle, at most the host's cores)")
+    ap.add_argument("--no-served", dest="served_legs", action="store_false",
+                    help="skip the served legs of the default run")
+    ap.add_argument("--serve-duration", type=float, default=20.0,
+                    help="seconds of arrivals per served leg of the default run")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--precision", choices=("plain", "bf16x3"), default="plain",
                     help="plain: FP32 expansion; bf16x3: BF16 MFMA expansion for the coarse bands "
@@ -164,6 +208,9 @@ def main():
                     help="serving: particles admitted per box edge per tick")
     ap.add_argument("--pool", type=int, default=16,
                     help="serving: pre-rendered particles per (box, template)")
+    ap.add_argument("--select-bands", action="store_true",
+                    help="serving, paper method: bands chosen by the library from the templates' "
+                         "energy ratio (--ratio-thresholds) instead of the fixed 6-11-L")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -335,8 +382,15 @@ def main():
         result["accuracy"]["p99_deg_vs_plain_path"] = round(float(np.percentile(dp, 99)), 4)
         result["accuracy"]["frac_within_0.5deg_of_plain"] = round(float(np.mean(dp <= 0.5)), 4)
 
+    if args.served_legs:
+        result["served"] = served_legs(args, value)
+
     if args.cpu_sample > 0:
-        dt, cpu, e_oracle, A_oracle = cpu_baseline(w, args.cpu_sample)
+        n_cpu = os.cpu_count() or 1
+        workers = max(1, min(args.cpu_sample, args.cpu_workers or n_cpu))
+        print(f"# oracle on {args.cpu_sample} particles, {workers} worker processes",
+              file=sys.stderr, flush=True)
+        dt, cpu, e_oracle, A_oracle, t_exp, march_s = cpu_baseline(w, args.cpu_sample, workers)
         ang_o = geodesic_deg(e_oracle, eu_h[:args.cpu_sample])
         n_s = args.cpu_sample
         ref_norm = np.linalg.norm(A_oracle, axis=1)
@@ -347,11 +401,16 @@ def main():
         result["cpu_baseline"] = {
             "value": round(args.cpu_sample / dt, 5),
             "unit": "subtomograms/s",
-            "cores": max(1, int(round(cpu / dt))),
+            "cores": workers,
             "kind": "oracle",
-            "sample": f"first {args.cpu_sample} particle(s) of the workload: FP64 oracle expansion "
-                      f"(64^3, L=32) + 64-restart march, bands 8-16-24-32, 20 steps; "
-                      f"{dt:.1f} s wall, {cpu:.1f} s CPU on {os.cpu_count()} visible cores",
+            "per_core": round(args.cpu_sample / dt / workers, 6),
+            "sample": f"first {args.cpu_sample} particles of the workload: FP64 oracle expansion "
+                      f"of the template and the particles in one call (64^3, L=32; {t_exp:.1f} s), "
+                      f"then each particle's 64-restart march (bands 8-16-24-32, 20 steps; "
+                      f"{np.mean(march_s):.1f} s each) in {workers} worker processes; "
+                      f"{dt:.1f} s wall, {cpu:.1f} s CPU",
+            "host": {"cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+                     "workers": workers, "blas_threads_per_process": 1},
         }
         result["accuracy"]["max_deg_vs_oracle_on_sample"] = round(float(ang_o.max()), 4)
     plan.close()
@@ -562,54 +621,65 @@ SERVE_PLANS = {32: (16, (8, 16)), 48: (24, (8, 16, 24)), 64: (32, (8, 16, 24, 32
 SERVE_PAPER_BANDS = {32: (6, 11, 16), 48: (6, 11, 24), 64: (6, 11, 32), 96: (6, 11, 40)}
 
 
-def serve_bench(args):
-    """Serving loop on a Poisson stream of requests (mixed box edges, 8
-    resident templates).  Prints one JSON line: offered and sustained
-    throughput, latency percentiles, accuracy against the planted rotations,
-    and the plain batch path's throughput at 64^3 for comparison."""
+class ServingSetup:
+    """Pre-rendered particle pools, start pool, plans and resident templates
+    of the serving workload (8 blob templates; box edges as given)."""
+
+    def __init__(self, boxes, pool: int, threads: int, P: int = 64):
+        import torch
+        import synth.serving as ss
+        from paper_2509_01180_amd.api import Plan
+        self.dev = dev = torch.device("cuda:0")
+        self.boxes, self.pool, self.P = list(boxes), int(pool), int(P)
+        self.blobs = ss.serving_templates()
+        nt = len(self.blobs)
+        t_gen = time.perf_counter()
+        self.pools, self.truth = {}, {}
+        with ThreadPoolExecutor(max(1, threads)) as ex:
+            for N in self.boxes:
+                jobs = [(t, j) for t in range(nt) for j in range(self.pool)]
+                vols = list(ex.map(lambda tj: ss.pool_particle(self.blobs[tj[0]], N, tj[0], tj[1]),
+                                   jobs))
+                self.pools[N] = torch.from_numpy(np.stack(vols)).to(dev)
+                self.truth[N] = np.stack([ss.pool_rotation(N, t, j) for t, j in jobs])
+                del vols
+                print(f"# pool of {len(jobs)} particles at {N}^3 ready", file=sys.stderr, flush=True)
+        self.start_pool = torch.from_numpy(ss.start_pool(4096, self.P)).to(dev)
+        self.t_gen = time.perf_counter() - t_gen
+        t_plan = time.perf_counter()
+        self.plans, self.tmpls = {}, {}
+        for N in self.boxes:
+            L, _bands = SERVE_PLANS[N]
+            self.plans[N] = Plan(N, L, device=0)
+            tv = np.stack([synth.render_blobs(b, N) for b in self.blobs]).astype(np.float32)
+            self.tmpls[N] = self.plans[N].expand(torch.from_numpy(tv).to(dev))
+        torch.cuda.synchronize()
+        self.t_plan = time.perf_counter() - t_plan
+        print(f"# plans built in {self.t_plan:.1f} s", file=sys.stderr, flush=True)
+
+    def close(self):
+        for p in self.plans.values():
+            p.close()
+
+
+def serving_run(S: ServingSetup, boxes, method: str, rate: float, duration: float,
+                T: int = 20, budget_gib: float = 24.0, max_cohort: int = 2048, keep: int = 8,
+                newton_steps: int = 6, band_thresholds=None, seed: int = 0) -> dict:
+    """One run of the serving loop on a Poisson request stream: offered and
+    sustained throughput, latency percentiles (completion minus arrival,
+    from GPU event timestamps), accuracy against the planted rotations."""
     import torch
     import synth.serving as ss
-    from paper_2509_01180_amd.api import Plan
     from paper_2509_01180_amd.serving import Engine, Request, latency_summary
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    boxes = [int(x) for x in args.boxes.split(",")]
-    P, T = 64, 20
-    blobs = ss.serving_templates()
-    nt = len(blobs)
-    t_gen = time.perf_counter()
-    pools, truth = {}, {}
-    with ThreadPoolExecutor(max(1, args.threads)) as ex:
-        for N in boxes:
-            jobs = [(t, j) for t in range(nt) for j in range(args.pool)]
-            vols = list(ex.map(lambda tj: ss.pool_particle(blobs[tj[0]], N, tj[0], tj[1]), jobs))
-            pools[N] = torch.from_numpy(np.stack(vols)).to(dev)
-            truth[N] = np.stack([ss.pool_rotation(N, t, j) for t, j in jobs])
-            del vols
-            print(f"# pool of {len(jobs)} particles at {N}^3 ready", file=sys.stderr, flush=True)
-    start_pool = torch.from_numpy(ss.start_pool(4096, P)).to(dev)
-    t_gen = time.perf_counter() - t_gen
-
-    t_plan = time.perf_counter()
-    plans, tmpls = {}, {}
-    for N in boxes:
-        L, _bands = SERVE_PLANS[N]
-        plans[N] = Plan(N, L, device=0)
-        tv = np.stack([synth.render_blobs(b, N) for b in blobs]).astype(np.float32)
-        tmpls[N] = plans[N].expand(torch.from_numpy(tv).to(dev))
-    torch.cuda.synchronize()
-    t_plan = time.perf_counter() - t_plan
-    print(f"# plans built in {t_plan:.1f} s", file=sys.stderr, flush=True)
-
-    if args.method == "paper":
+    dev, P, pool = S.dev, S.P, S.pool
+    if method == "paper" and band_thresholds is None:
         boxes_cfg = {N: (SERVE_PLANS[N][0], SERVE_PAPER_BANDS[N]) for N in boxes}
     else:
         boxes_cfg = {N: SERVE_PLANS[N] for N in boxes}
-    eng = Engine(boxes_cfg, tmpls, restarts=P, steps=T,
-                 budget_bytes=int(args.budget_gib * (1 << 30)), max_cohort=args.max_cohort,
-                 plans=plans, method=args.method, keep=args.keep,
-                 newton_steps=args.newton_steps)
+    eng = Engine(boxes_cfg, {N: S.tmpls[N] for N in boxes}, restarts=P, steps=T,
+                 budget_bytes=int(budget_gib * (1 << 30)), max_cohort=max_cohort,
+                 plans={N: S.plans[N] for N in boxes}, method=method, keep=keep,
+                 newton_steps=newton_steps, band_thresholds=band_thresholds)
 
     def make_request(spec, arrival=None):
         # the index tensors are made inside the callables, which the engine
@@ -617,12 +687,12 @@ def serve_bench(args):
         N, t, n = spec.box, spec.template, spec.n
 
         def volumes():
-            j = (spec.offset + torch.arange(n, device=dev)) % args.pool + t * args.pool
-            return pools[N].index_select(0, j)
+            j = (spec.offset + torch.arange(n, device=dev)) % pool + t * pool
+            return S.pools[N].index_select(0, j)
 
         def starts():
-            k = (spec.start_offset + torch.arange(n, device=dev)) % start_pool.shape[0]
-            return start_pool.index_select(0, k)
+            k = (spec.start_offset + torch.arange(n, device=dev)) % S.start_pool.shape[0]
+            return S.start_pool.index_select(0, k)
 
         return Request(box=N, template=t, n=n, rid=spec.rid, arrival=arrival,
                        volumes=volumes, starts=starts)
@@ -633,25 +703,25 @@ def serve_bench(args):
         eng.submit(make_request(ss.RequestSpec(-1 - i, 0.0, N, 0, 4, 0, 0)))
     eng.drain()
 
-    reqs = ss.request_stream(args.rate, args.duration, boxes, seed=0, pool=args.pool)
-    print(f"# {len(reqs)} requests, {sum(r.n for r in reqs)} particles over {args.duration} s "
-          f"at {args.rate}/s", file=sys.stderr, flush=True)
+    reqs = ss.request_stream(rate, duration, boxes, seed=seed, pool=pool)
+    print(f"# serving ({method}, boxes {list(boxes)}): {len(reqs)} requests, "
+          f"{sum(r.n for r in reqs)} particles over {duration} s at {rate}/s",
+          file=sys.stderr, flush=True)
     done = []
-    submitted = []
     i = 0
     t0 = time.perf_counter()
     last_note = t0
     ticks = 0
     while True:
         now = time.perf_counter() - t0
-        if now >= args.duration:
+        if now >= duration:
             break
         while i < len(reqs) and reqs[i].arrival <= now:
-            submitted.append(eng.submit(make_request(reqs[i], t0 + reqs[i].arrival)))
+            eng.submit(make_request(reqs[i], t0 + reqs[i].arrival))
             i += 1
         if not eng.sched.busy():
             done += eng.step()          # collects finished cohorts, no device work
-            nxt = reqs[i].arrival if i < len(reqs) else args.duration
+            nxt = reqs[i].arrival if i < len(reqs) else duration
             time.sleep(max(0.0, min(nxt - now, 0.002)))
             continue
         done += eng.step()
@@ -667,14 +737,14 @@ def serve_bench(args):
     eng.sched.queue.clear()
     done += eng.drain()
 
-    warm = min(5.0, 0.2 * args.duration)
+    warm = min(5.0, 0.2 * duration)
     win = [r for r in done if r.done is not None and t0 + warm <= r.done <= t_end]
     span = (t_end - t0) - warm
     sustained = sum(r.n for r in win) / span
-    offered = sum(r.n for r in reqs) / args.duration
+    offered = sum(r.n for r in reqs) / duration
     lat_all = latency_summary([r for r in done if r.arrival >= t0 + warm and r.done <= t_end])
-
     per_box = {}
+    all_ang = []
     for N in boxes:
         rs = [r for r in win if r.box == N]
         ang = []
@@ -682,54 +752,123 @@ def serve_bench(args):
             if r.box != N or r.euler is None or r.rid < 0:
                 continue
             sp = reqs[r.rid]
-            jj = (sp.offset + np.arange(r.n)) % args.pool + sp.template * args.pool
+            jj = (sp.offset + np.arange(r.n)) % pool + sp.template * pool
             R_est = synth.euler_zyz_to_matrix(r.euler)
-            d = np.linalg.norm(R_est - np.transpose(truth[N][jj], (0, 2, 1)), axis=(1, 2))
+            d = np.linalg.norm(R_est - np.transpose(S.truth[N][jj], (0, 2, 1)), axis=(1, 2))
             ang.append(np.degrees(2 * np.arcsin(np.minimum(1.0, d / (2 * np.sqrt(2))))))
         ang = np.concatenate(ang) if ang else np.zeros(0)
+        all_ang.append(ang)
         per_box[str(N)] = {
-            "L_max": SERVE_PLANS[N][0], "bands": list(boxes_cfg[N][1]),
-            "offered_per_s": round(sum(r.n for r in reqs if r.box == N) / args.duration, 1),
+            "L_max": SERVE_PLANS[N][0], "bands": list(eng.sched.specs[N].bands),
+            "offered_per_s": round(sum(r.n for r in reqs if r.box == N) / duration, 1),
             "sustained_per_s": round(sum(r.n for r in rs) / span, 1),
             "latency": latency_summary([r for r in rs if r.arrival >= t0 + warm]),
             "median_deg_vs_planted": round(float(np.median(ang)), 3) if ang.size else None,
             "p90_deg_vs_planted": round(float(np.percentile(ang, 90)), 3) if ang.size else None,
         }
+    all_ang = np.concatenate(all_ang) if all_ang else np.zeros(0)
+    out = {
+        "served_per_s": round(sustained, 1),
+        "offered_per_s": round(offered, 1),
+        "latency": lat_all,
+        "backlog_at_end": {"queued_particles": backlog_queued, "in_flight_particles": backlog_live},
+        "median_deg_vs_planted": round(float(np.median(all_ang)), 3) if all_ang.size else None,
+        "per_box": per_box, "ticks": ticks, "method": method, "rate_per_s": rate,
+        "duration_s": duration, "warmup_excluded_s": warm,
+    }
+    eng.sched.queue.clear()
+    return out
 
-    plain = None
-    if 64 in boxes:
-        # the plain batch path (FP32 expansion, one template, 1000 particles
-        # per call) on the same particles, for the served-vs-plain comparison
-        plan = plans[64]
-        L, bands = SERVE_PLANS[64]
-        jj = torch.arange(1000, device=dev) % (nt * args.pool)
-        vols = pools[64].index_select(0, jj)
-        st = start_pool[:1000].contiguous()
-        b = tmpls[64][0].contiguous()
-        a = torch.empty((1000, plan.C, 2), dtype=torch.float32, device=dev)
+
+def plain_rate_64(S: ServingSetup, T: int = 20) -> float:
+    """The plain batch path (FP32 expansion, one template, 1000 particles
+    per call) on the serving pool's 64^3 particles, subtomograms/s."""
+    import torch
+    plan = S.plans[64]
+    L, bands = SERVE_PLANS[64]
+    nt = len(S.blobs)
+    jj = torch.arange(1000, device=S.dev) % (nt * S.pool)
+    vols = S.pools[64].index_select(0, jj)
+    st = S.start_pool[:1000].contiguous()
+    b = S.tmpls[64][0].contiguous()
+    a = torch.empty((1000, plan.C, 2), dtype=torch.float32, device=S.dev)
+    plan.expand(vols, out=a)
+    plan.align(a, b, bands, st, T)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for _ in range(3):
         plan.expand(vols, out=a)
         plan.align(a, b, bands, st, T)
-        torch.cuda.synchronize()
-        tp = time.perf_counter()
-        for _ in range(3):
-            plan.expand(vols, out=a)
-            plan.align(a, b, bands, st, T)
-        torch.cuda.synchronize()
-        plain = 3000 / (time.perf_counter() - tp)
-        del vols, a
+    torch.cuda.synchronize()
+    return 3000 / (time.perf_counter() - tp)
 
+
+SERVED_LEG_THRESHOLDS = (0.01, 0.001)
+
+
+def served_legs(args, plain_value: float) -> dict:
+    """The served legs of the default run: the 64^3 box alone at an offered
+    load above capacity (saturated), and the mixed-box Poisson stream of
+    200 requests/s (U{1..512} particles, boxes 32/64/96, 8 templates), each
+    with the gradient march and with the paper's procedure (bands chosen by
+    the library from the templates' energy ratio, candidates, Newton
+    steps).  served/plain is served subtomograms/s over the plain batch
+    path's value of this run."""
+    S = ServingSetup([32, 64, 96], args.pool, args.threads)
+    legs = {
+        "64_saturated_march": ([64], "march", 400.0),
+        "64_saturated_paper": ([64], "paper", 1600.0),
+        "mixed_200rps_march": ([32, 64, 96], "march", 200.0),
+        "mixed_200rps_paper": ([32, 64, 96], "paper", 200.0),
+    }
+    out = {}
+    for name, (boxes, method, rate) in legs.items():
+        r = serving_run(S, boxes, method, rate, args.serve_duration, budget_gib=args.budget_gib,
+                        max_cohort=args.max_cohort, keep=args.keep,
+                        newton_steps=args.newton_steps,
+                        band_thresholds=SERVED_LEG_THRESHOLDS if method == "paper" else None)
+        r["served_over_plain"] = round(r["served_per_s"] / plain_value, 3)
+        out[name] = {k: r[k] for k in ("served_per_s", "offered_per_s", "served_over_plain",
+                                       "latency", "median_deg_vs_planted", "backlog_at_end",
+                                       "rate_per_s", "duration_s")}
+        out[name]["bands"] = {N: v["bands"] for N, v in r["per_box"].items()}
+        print(f"# served leg {name}: {r['served_per_s']}/s of {r['offered_per_s']}/s offered, "
+              f"p50 {r['latency'].get('p50_ms')} ms, p99 {r['latency'].get('p99_ms')} ms",
+              file=sys.stderr, flush=True)
+    out["setup"] = {"pool_generation_s": round(S.t_gen, 1), "plan_build_s": round(S.t_plan, 1),
+                    "paper_band_thresholds": list(SERVED_LEG_THRESHOLDS)}
+    S.close()
+    return out
+
+
+def serve_bench(args):
+    """Serving loop on a Poisson stream of requests (mixed box edges, 8
+    resident templates).  Prints one JSON line: offered and sustained
+    throughput, latency percentiles, accuracy against the planted rotations,
+    and the plain batch path's throughput at 64^3 for comparison."""
+    import torch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    boxes = [int(x) for x in args.boxes.split(",")]
+    S = ServingSetup(boxes, args.pool, args.threads)
+    thresholds = (tuple(float(x) for x in args.ratio_thresholds.split(","))
+                  if args.select_bands else None)
+    r = serving_run(S, boxes, args.method, args.rate, args.duration, budget_gib=args.budget_gib,
+                    max_cohort=args.max_cohort, keep=args.keep, newton_steps=args.newton_steps,
+                    band_thresholds=thresholds if args.method == "paper" else None)
+    plain = plain_rate_64(S) if 64 in boxes else None
     result = {
         "metric": "served subtomograms/s (Poisson arrivals, mixed box edges, 8 templates)",
-        "value": round(sustained, 1),
+        "value": r["served_per_s"],
         "unit": "subtomograms/s",
         "n_gpus": 1,
         "higher_is_better": True,
-        "offered_per_s": round(offered, 1),
-        "backlog_at_end": {"queued_particles": backlog_queued, "in_flight_particles": backlog_live},
-        "latency": lat_all,
-        "per_box": per_box,
+        "offered_per_s": r["offered_per_s"],
+        "backlog_at_end": r["backlog_at_end"],
+        "latency": r["latency"],
+        "per_box": r["per_box"],
         "plain_path_64_per_s": round(plain, 1) if plain else None,
-        "ticks": ticks,
+        "ticks": r["ticks"],
         "dtype": "bf16x3 expansion (bf16 coarse bands, refined final band)/f64 score",
         "data": "synthetic",
         "config": {
@@ -740,13 +879,13 @@ def serve_bench(args):
                            f"; paper procedure: {args.keep} candidates after the lowest band, "
                            f"{args.newton_steps} Newton steps per higher band"),
             "method": args.method,
-            "duration_s": args.duration, "warmup_excluded_s": warm,
+            "duration_s": args.duration, "warmup_excluded_s": r["warmup_excluded_s"],
             "budget_gib": args.budget_gib, "max_cohort": args.max_cohort,
             "parallelism": "single GPU",
         },
-        "setup": {"pool_generation_s": round(t_gen, 1), "plan_build_s": round(t_plan, 1)},
+        "setup": {"pool_generation_s": round(S.t_gen, 1), "plan_build_s": round(S.t_plan, 1)},
     }
-    eng.close()
+    S.close()
     print(json.dumps(result), flush=True)
 
 

@@ -28,14 +28,24 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 
+# Per-source flags.  The score kernels are built without machine-level loop
+# invariant code motion: with it, the compiler hoists the FP64 constants of
+# the sine/cosine evaluations out of every loop and, short of registers,
+# spills them to scratch memory (112 bytes per lane in the ascent kernel,
+# whose stores reached HBM as hundreds of MB per launch); without it the
+# ascent kernel keeps one 8-byte value in scratch, stored once per wave.
+FILE_FLAGS: dict = {"bh_score.hip": ["-mllvm", "-disable-machine-licm"]}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                   if f.endswith((".hip", ".cpp")))
 
 
-def compile_one(src: str, build_dir: str = BUILD, defines=()) -> str:
+def compile_one(src: str, build_dir: str = BUILD, defines=(), extra=()) -> str:
     obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-    flags = [*COMMON, *[f"-D{d}" for d in defines]]
+    flags = [*COMMON, *FILE_FLAGS.get(os.path.basename(src), []), *extra,
+             *[f"-D{d}" for d in defines]]
     cmd = [HIPCC, *flags, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, *flags, "-x", "hip", "-c", src, "-o", obj]
@@ -49,12 +59,13 @@ def compile_one(src: str, build_dir: str = BUILD, defines=()) -> str:
 
 
 def build(jobs: int = 8, verbose: bool = True, out: str = LIB, build_dir: str = BUILD,
-          defines=()) -> str:
-    """Compile and link the library; `defines` are extra -D build parameters."""
+          defines=(), extra=()) -> str:
+    """Compile and link the library; `defines` are extra -D build parameters
+    and `extra` extra compiler flags (both for every source)."""
     os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(lambda s: compile_one(s, build_dir, defines), srcs))
+        objs = list(ex.map(lambda s: compile_one(s, build_dir, defines, extra), srcs))
     tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

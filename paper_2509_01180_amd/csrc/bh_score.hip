@@ -403,10 +403,11 @@ __global__ __launch_bounds__(64 * W) BH_MARCH_OCCUPANCY(NEWTON, G < 64) void k_m
   // the grid covers the batch, persistent workgroups when it is smaller.
   constexpr int64_t PER = (G == 64) ? 1 : 64 / G;
   for (int64_t base = blockIdx.y; base * PER < B; base += gridDim.y) {
-    int64_t pb, r;
+    int64_t pb;
+    int r;                            // restart (P <= 65536)
     if constexpr (G == 64) {
       pb = base;
-      r = (int64_t)blockIdx.x * 64 + lane;
+      r = (int)blockIdx.x * 64 + lane;
     } else {
       pb = base * PER + lane / G;
       r = lane % G;
@@ -492,12 +493,27 @@ __global__ __launch_bounds__(64 * W) BH_MARCH_OCCUPANCY(NEWTON, G < 64) void k_m
       }
       __syncthreads();
     }
-    if (wave == 0 && active) {
-      double* so = state + (pb * P + r) * 3;
-      so[0] = st[ST_XA * 64 + lane];
-      so[1] = st[ST_XB * 64 + lane];
-      so[2] = st[ST_XG * 64 + lane];
-      sscore[pb * P + r] = st[ST_S * 64 + lane];
+    if (wave == 0) {
+      if constexpr (G == 64) {
+        // the wave's end points [64][3] leave as three contiguous 512-byte
+        // runs read across the LDS state (whole cache lines, not three
+        // strided 8-byte stores per lane)
+        const int r0 = (int)blockIdx.x * 64;
+        const int n = 3 * min(64, P - r0);
+        double* so = state + (pb * P + r0) * 3;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int idx = k * 64 + lane;
+          if (idx < n) so[idx] = st[(ST_XA + idx % 3) * 64 + idx / 3];
+        }
+        if (active) sscore[pb * P + r] = st[ST_S * 64 + lane];
+      } else if (active) {
+        double* so = state + (pb * P + r) * 3;
+        so[0] = st[ST_XA * 64 + lane];
+        so[1] = st[ST_XB * 64 + lane];
+        so[2] = st[ST_XG * 64 + lane];
+        sscore[pb * P + r] = st[ST_S * 64 + lane];
+      }
     }
     __syncthreads();   // the next particle's set-up overwrites the ascent state
   }
