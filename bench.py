@@ -21,6 +21,7 @@ oracle on a bounded sample of the same workload on the host cores.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -59,9 +60,11 @@ def band_counts(L: int):
 
 
 def score_kernel_sources_hash() -> str:
+    """Hash of what the ascent kernel's machine code is built from (its
+    sources and the build flags)."""
     h = hashlib.sha256()
-    for f in ("bh_score.hip", "bh_eval.h"):
-        h.update(open(os.path.join(ROOT, "paper_2509_01180_amd", "csrc", f), "rb").read())
+    for f in ("csrc/bh_score.hip", "csrc/bh_eval.h", "csrc/bh_internal.h", "build.py"):
+        h.update(open(os.path.join(ROOT, "paper_2509_01180_amd", f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -275,9 +278,19 @@ def main():
         step()
     torch.cuda.synchronize()
     if args.calib_mib > 0:
-        src = torch.ones(args.calib_mib << 18, dtype=torch.float32, device=dev)
+        # reference kernels of known traffic for the hardware counters: a
+        # plain 16-byte-per-lane copy and a wave-uniform scalar read, each of
+        # calib_mib MiB (bh_calib_copy)
+        from paper_2509_01180_amd._lib import (BH_CALIB_COPY_VECTOR, BH_CALIB_READ_SCALAR,
+                                               check, lib)
+        nb = args.calib_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        st_ = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        check(lib().bh_calib_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                  nb, BH_CALIB_COPY_VECTOR, st_), "bh_calib_copy")
+        check(lib().bh_calib_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                  nb, BH_CALIB_READ_SCALAR, st_), "bh_calib_copy")
         torch.cuda.synchronize()
         del src, dst
 

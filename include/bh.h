@@ -410,6 +410,22 @@ int bh_profile_enable(bh_plan* p, int enable);
 int bh_profile_read(bh_plan* p, const char* name, int64_t* launches, double* total_ms,
                     int64_t* work);
 
+/* ---------------------------------------------------------------------
+ * Reference kernels for hardware traffic counters (measurement only): a
+ * counter's reading for a kernel that moves a known number of bytes in the
+ * same way scales the counter's readings for the library's kernels.
+ *  BH_CALIB_COPY_VECTOR: copy `bytes` (a multiple of 16) from src to dst,
+ *      16 bytes per lane per load and store (dev buffers of `bytes`);
+ *  BH_CALIB_READ_SCALAR: read `bytes` (a multiple of 64) of src in
+ *      wave-uniform 64-byte loads through the scalar cache, as the ascent
+ *      kernel reads its class weights; dst (dev double[BH_CALIB_READ_GROUPS])
+ *      receives one sum per workgroup.
+ * Asynchronous on `stream`.
+ * ------------------------------------------------------------------- */
+enum { BH_CALIB_COPY_VECTOR = 0, BH_CALIB_READ_SCALAR = 1 };
+#define BH_CALIB_READ_GROUPS 2048
+int bh_calib_copy(void* dst, const void* src, int64_t bytes, int mode, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,8 @@ BH_OK, BH_EINVAL, BH_ENOMEM, BH_EDEVICE, BH_EUNSUPPORTED = 0, -1, -2, -3, -4
 BH_EXPAND_FP32, BH_EXPAND_BF16, BH_EXPAND_BF16X3 = 0, 1, 2
 BH_EXPAND_BATCH_INVARIANT = 16
 BH_TUNE_MARCH, BH_TUNE_EXPAND, BH_TUNE_EXPAND_BF16 = 1, 2, 4
+BH_CALIB_COPY_VECTOR, BH_CALIB_READ_SCALAR = 0, 1
+BH_CALIB_READ_GROUPS = 2048
 BH_MAX_L = 64
 BH_MAX_N = 256
 
@@ -83,6 +85,7 @@ SIGNATURES = {
     "bh_plan_tuning": (_I, [_P, _I, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
                             ctypes.POINTER(_I)]),
     "bh_plan_set_tuning": (_I, [_P, _I, _I, _I]),
+    "bh_calib_copy": (_I, [_P, _P, _I64, _I, _P]),
     "bh_profile_enable": (_I, [_P, _I]),
     "bh_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(_I64)]),
