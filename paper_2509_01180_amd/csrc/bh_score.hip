@@ -259,6 +259,15 @@ __device__ inline Acc sum_partials(const double* buf, int lane, int W) {
   return Acc{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9]};
 }
 
+// This lane's index in its wave, computed where it is called from the lane
+// masks (v_mbcnt): the compiler cannot hoist it, so values derived from it
+// are not held through loops (and spilled) either.
+__device__ inline int lane_index() {
+  int v;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(v));
+  return v;
+}
+
 __device__ inline double wrap_pi(double t) { return t - kTwoPi * floor((t + kPi) / kTwoPi); }
 
 __device__ inline void wrap_euler(double& a, double& b, double& g) {
@@ -403,14 +412,20 @@ __global__ __launch_bounds__(64 * W) BH_MARCH_OCCUPANCY(NEWTON, G < 64) void k_m
   // the grid covers the batch, persistent workgroups when it is smaller.
   constexpr int64_t PER = (G == 64) ? 1 : 64 / G;
   for (int64_t base = blockIdx.y; base * PER < B; base += gridDim.y) {
+    // The index arithmetic of the per-particle state I/O derives from an
+    // opaque copy of the lane index (recomputed from the lane masks, not
+    // kept from the kernel's start), so the compiler keeps it inside the
+    // particle loop: hoisted out of it, it would be held in scratch memory
+    // (written by each of the launch's waves).
+    const int lane_o = lane_index();
     int64_t pb;
     int r;                            // restart (P <= 65536)
     if constexpr (G == 64) {
       pb = base;
-      r = (int)blockIdx.x * 64 + lane;
+      r = (int)blockIdx.x * 64 + lane_o;
     } else {
-      pb = base * PER + lane / G;
-      r = lane % G;
+      pb = base * PER + lane_o / G;
+      r = lane_o % G;
     }
     const bool active = pb < B && r < P;
     if (pb >= B) pb = B - 1;          // idle lanes read a valid particle
@@ -494,25 +509,31 @@ __global__ __launch_bounds__(64 * W) BH_MARCH_OCCUPANCY(NEWTON, G < 64) void k_m
       __syncthreads();
     }
     if (wave == 0) {
+      // indices re-derived from a fresh opaque lane copy (see above)
+      const int lane_e = lane_index();
       if constexpr (G == 64) {
         // the wave's end points [64][3] leave as three contiguous 512-byte
         // runs read across the LDS state (whole cache lines, not three
         // strided 8-byte stores per lane)
         const int r0 = (int)blockIdx.x * 64;
         const int n = 3 * min(64, P - r0);
-        double* so = state + (pb * P + r0) * 3;
+        double* so = state + (base * P + r0) * 3;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const int idx = k * 64 + lane;
+          const int idx = k * 64 + lane_e;
           if (idx < n) so[idx] = st[(ST_XA + idx % 3) * 64 + idx / 3];
         }
-        if (active) sscore[pb * P + r] = st[ST_S * 64 + lane];
-      } else if (active) {
-        double* so = state + (pb * P + r) * 3;
-        so[0] = st[ST_XA * 64 + lane];
-        so[1] = st[ST_XB * 64 + lane];
-        so[2] = st[ST_XG * 64 + lane];
-        sscore[pb * P + r] = st[ST_S * 64 + lane];
+        if (r0 + lane_e < P) sscore[base * P + r0 + lane_e] = st[ST_S * 64 + lane_e];
+      } else {
+        const int64_t pe = base * PER + lane_e / G;
+        const int re = lane_e % G;
+        if (pe < B && re < P) {
+          double* so = state + (pe * P + re) * 3;
+          so[0] = st[ST_XA * 64 + lane_e];
+          so[1] = st[ST_XB * 64 + lane_e];
+          so[2] = st[ST_XG * 64 + lane_e];
+          sscore[pe * P + re] = st[ST_S * 64 + lane_e];
+        }
       }
     }
     __syncthreads();   // the next particle's set-up overwrites the ascent state
