@@ -102,9 +102,16 @@ struct StepLds {
   static constexpr int bytes = (LO ? 4 : 2) * kArrBytes;
 };
 
-// Chunk c of row r sits at chunk position c ^ ((r >> 1) & 3): the 16-byte
-// fragment reads of eight consecutive rows then hit distinct bank groups.
-__device__ inline int step_swz(int c, int r) { return c ^ ((r >> 1) & 3); }
+// Chunk c of row r sits at chunk position c ^ g(r), g(r) = (r1 ^ r3) + 2 r2
+// for the bits r1..r3 of r: the 16-byte fragment reads of any eight
+// consecutive rows fall in distinct 16-byte bank groups of a 128-byte span,
+// and those of any sixteen in distinct ones of a 256-byte span (rows are
+// 64 bytes, so rows r and r + 4 share banks).  The previous g(r) = r1 + 2 r2
+// gave sixteen rows two-way conflicts (measured: bank-conflict cycles four
+// times the LDS instruction cycles).
+__device__ inline int step_swz(int c, int r) {
+  return c ^ ((((r >> 1) ^ (r >> 3)) & 1) | (((r >> 2) & 1) << 1));
+}
 
 // Wait for this wave's LDS reads and LDS-DMA loads, then the barrier.
 // (Written out: the compiler's barrier adds nothing here, and its own wait
