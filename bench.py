@@ -454,12 +454,13 @@ def paper_bench(args):
     b = plan.expand(torch.from_numpy(w.template_volume()[None]).to(dev))[0].contiguous()
     a = torch.empty((B, plan.C, 2), dtype=torch.float32, device=dev)
     plan.expand(vols, out=a)
-    E = plan.degree_energy(a, b, w.L_max).cpu().numpy()
-    tot = E.sum(axis=1, keepdims=True)
-    ratio = np.median((tot - np.cumsum(E, axis=1)) / np.maximum(tot, 1e-300), axis=0)
+    # bands from the energy ratio of the batch's cross-power, chosen by the
+    # library (bh_select_bands: per threshold, the smallest band that leaves
+    # at most that fraction out for at least half the particles)
     taus = [float(x) for x in args.ratio_thresholds.split(",")]
-    bands = sorted({int(np.nonzero(ratio <= t)[0][0]) for t in taus} | {w.L_max})
-    bands = [max(L, 1) for L in bands]
+    _bp, common, ratio_t = plan.select_bands(a, b, None, w.L_max, taus, ratio=True)
+    bands = Plan.schedule(common.cpu().tolist(), w.L_max)
+    ratio = ratio_t.median(dim=0).values.cpu().numpy()
     opts = dict(newton_bands=len(bands) - 1, newton_steps=args.newton_steps, keep=args.keep,
                 min_sep=np.radians(10.0))
 
@@ -512,7 +513,8 @@ def paper_bench(args):
                                f"64 starts x {w.steps} gradient steps on band {bands[0]}, "
                                f"{args.keep} candidates (10 deg apart), "
                                f"{args.newton_steps} Newton steps per higher band",
-                   "bands": bands, "median_energy_ratio": [round(float(x), 5) for x in ratio]},
+                   "bands": bands, "band_choice": "bh_select_bands (batch: at least half the particles)",
+                   "median_energy_ratio": [round(float(x), 5) for x in ratio]},
         "kernels_ms_per_step": kern,
         "plain_march": {"value": round(B / (ms_plain / 1e3), 2), "ms_per_step": round(ms_plain, 3)},
         "accuracy": {"median_deg_vs_planted": round(float(np.median(ang)), 3),
