@@ -137,6 +137,147 @@ struct Acc {
     EB = fma(u_, EA, -EB);                                                    \
   } while (0)
 
+#if defined(__HIP_DEVICE_COMPILE__)
+// The chain sums of one class for wave-uniform weights, as one asm block:
+// t = sum_l X_l e_l and r = sum_l X_l de_l/dx over the chain's n entries,
+// from the seeds (e_m, de_m/dx) = (eb, rb), in rounds of four entries.
+// Each round fetches its four X entries (32 B each) and recurrence entries
+// {ap, bq} (16 B each) with three 64-byte scalar loads into s36..s83 and
+// waits once; the first round also does the peeled first entry, so a chain
+// of n entries waits ceil(n / 4) times (against one wait for the peeled
+// entry, one per full round and one per tail of two or one entries in the
+// compiled loop, where the compiler also moves each load into the branch
+// that first uses it).  The last entry adds to the sums only.  Loads read
+// up to three entries past the chain (the next class's, or the tables'
+// padding); every load is waited for inside the block.  The arithmetic
+// and its order per value are those of the compiled loop: u = ap (x - bq),
+// r' = fma(ap, e, fma(u, r, -r_prev)), e' = fma(u, e, -e_prev), sums by
+// fma, the first entry's terms by products.
+#define BH_CA_ACC(XA, XB, XC, XD, EA, RA)      \
+  "v_fmac_f64 %[t1r], " XA ", %[" EA "]\n"     \
+  "v_fmac_f64 %[t1i], " XB ", %[" EA "]\n"     \
+  "v_fmac_f64 %[t2r], " XC ", %[" EA "]\n"     \
+  "v_fmac_f64 %[t2i], " XD ", %[" EA "]\n"     \
+  "v_fmac_f64 %[r1r], " XA ", %[" RA "]\n"     \
+  "v_fmac_f64 %[r1i], " XB ", %[" RA "]\n"     \
+  "v_fmac_f64 %[r2r], " XC ", %[" RA "]\n"     \
+  "v_fmac_f64 %[r2i], " XD ", %[" RA "]\n"
+#define BH_CA_STEP(XA, XB, XC, XD, AP, BQ, EA, RA, EB, RB)  \
+  "v_add_f64 %[u], %[x], -" BQ "\n"                         \
+  "v_mul_f64 %[u], " AP ", %[u]\n"                          \
+  BH_CA_ACC(XA, XB, XC, XD, EA, RA)                         \
+  "v_fma_f64 %[" RB "], %[u], %[" RA "], -%[" RB "]\n"      \
+  "v_fmac_f64 %[" RB "], " AP ", %[" EA "]\n"               \
+  "v_fma_f64 %[" EB "], %[u], %[" EA "], -%[" EB "]\n"
+#define BH_CA_ACC_(...) BH_CA_ACC(__VA_ARGS__)
+#define BH_CA_STEP_(...) BH_CA_STEP(__VA_ARGS__)
+// round entry j: X at s[36 + 8j ...], {ap, bq} at s[68 + 4j ...]
+#define BH_CA_X0 "s[36:37]", "s[38:39]", "s[40:41]", "s[42:43]"
+#define BH_CA_X1 "s[44:45]", "s[46:47]", "s[48:49]", "s[50:51]"
+#define BH_CA_X2 "s[52:53]", "s[54:55]", "s[56:57]", "s[58:59]"
+#define BH_CA_X3 "s[60:61]", "s[62:63]", "s[64:65]", "s[66:67]"
+#define BH_CA_E0 BH_CA_X0, "s[68:69]", "s[70:71]"
+#define BH_CA_E1 BH_CA_X1, "s[72:73]", "s[74:75]"
+#define BH_CA_E2 BH_CA_X2, "s[76:77]", "s[78:79]"
+#define BH_CA_E3 BH_CA_X3, "s[80:81]", "s[82:83]"
+#define BH_CA_LOAD                                  \
+  "s_add_u32 s85, s84, 0x40\n"                      \
+  "s_load_dwordx16 s[36:51], %[xc], s84\n"          \
+  "s_load_dwordx16 s[52:67], %[xc], s85\n"          \
+  "s_load_dwordx16 s[68:83], %[rc], s86\n"          \
+  "s_waitcnt lgkmcnt(0)\n"
+
+__device__ inline void chain_sums_asm(const void* xc, const void* rc, int n, double x, double eb,
+                                      double rb, double& t1r, double& t1i, double& t2r,
+                                      double& t2i, double& r1r, double& r1i, double& r2r,
+                                      double& r2i) {
+  double ea, ra, u;
+  asm volatile(
+      "s_mov_b32 s84, 0\n"
+      "s_mov_b32 s86, 0\n"
+      BH_CA_LOAD
+      "v_mul_f64 %[t1r], s[36:37], %[eb]\n"
+      "v_mul_f64 %[t1i], s[38:39], %[eb]\n"
+      "v_mul_f64 %[t2r], s[40:41], %[eb]\n"
+      "v_mul_f64 %[t2i], s[42:43], %[eb]\n"
+      "v_mul_f64 %[r1r], s[36:37], %[rb]\n"
+      "v_mul_f64 %[r1i], s[38:39], %[rb]\n"
+      "v_mul_f64 %[r2r], s[40:41], %[rb]\n"
+      "v_mul_f64 %[r2i], s[42:43], %[rb]\n"
+      "s_cmp_eq_u32 %[n], 1\n"
+      "s_cbranch_scc1 .Lbhc_end%=\n"
+      "v_add_f64 %[u], %[x], -s[70:71]\n"
+      "v_mul_f64 %[u], s[68:69], %[u]\n"
+      "v_mul_f64 %[ea], %[u], %[eb]\n"
+      "v_mul_f64 %[ra], %[u], %[rb]\n"
+      "v_fmac_f64 %[ra], s[68:69], %[eb]\n"
+      "s_cmp_eq_u32 %[n], 2\n"
+      "s_cbranch_scc1 .Lbhc_f2%=\n"
+      BH_CA_STEP_(BH_CA_E1, "ea", "ra", "eb", "rb")
+      "s_cmp_eq_u32 %[n], 3\n"
+      "s_cbranch_scc1 .Lbhc_f3%=\n"
+      BH_CA_STEP_(BH_CA_E2, "eb", "rb", "ea", "ra")
+      "s_cmp_eq_u32 %[n], 4\n"
+      "s_cbranch_scc1 .Lbhc_f4%=\n"
+      BH_CA_STEP_(BH_CA_E3, "ea", "ra", "eb", "rb")
+      "s_sub_u32 %[n], %[n], 4\n"
+      ".Lbhc_loop%=:\n"
+      "s_add_u32 s84, s84, 0x80\n"
+      "s_add_u32 s86, s86, 0x40\n"
+      BH_CA_LOAD
+      "s_cmp_le_i32 %[n], 4\n"
+      "s_cbranch_scc1 .Lbhc_last%=\n"
+      BH_CA_STEP_(BH_CA_E0, "eb", "rb", "ea", "ra")
+      BH_CA_STEP_(BH_CA_E1, "ea", "ra", "eb", "rb")
+      BH_CA_STEP_(BH_CA_E2, "eb", "rb", "ea", "ra")
+      BH_CA_STEP_(BH_CA_E3, "ea", "ra", "eb", "rb")
+      "s_sub_u32 %[n], %[n], 4\n"
+      "s_branch .Lbhc_loop%=\n"
+      ".Lbhc_last%=:\n"
+      "s_cmp_eq_u32 %[n], 1\n"
+      "s_cbranch_scc1 .Lbhc_l1%=\n"
+      BH_CA_STEP_(BH_CA_E0, "eb", "rb", "ea", "ra")
+      "s_cmp_eq_u32 %[n], 2\n"
+      "s_cbranch_scc1 .Lbhc_l2%=\n"
+      BH_CA_STEP_(BH_CA_E1, "ea", "ra", "eb", "rb")
+      "s_cmp_eq_u32 %[n], 3\n"
+      "s_cbranch_scc1 .Lbhc_l3%=\n"
+      BH_CA_STEP_(BH_CA_E2, "eb", "rb", "ea", "ra")
+      BH_CA_ACC_(BH_CA_X3, "ea", "ra")
+      "s_branch .Lbhc_end%=\n"
+      ".Lbhc_f2%=:\n"
+      BH_CA_ACC_(BH_CA_X1, "ea", "ra")
+      "s_branch .Lbhc_end%=\n"
+      ".Lbhc_f3%=:\n"
+      BH_CA_ACC_(BH_CA_X2, "eb", "rb")
+      "s_branch .Lbhc_end%=\n"
+      ".Lbhc_f4%=:\n"
+      BH_CA_ACC_(BH_CA_X3, "ea", "ra")
+      "s_branch .Lbhc_end%=\n"
+      ".Lbhc_l1%=:\n"
+      BH_CA_ACC_(BH_CA_X0, "eb", "rb")
+      "s_branch .Lbhc_end%=\n"
+      ".Lbhc_l2%=:\n"
+      BH_CA_ACC_(BH_CA_X1, "ea", "ra")
+      "s_branch .Lbhc_end%=\n"
+      ".Lbhc_l3%=:\n"
+      BH_CA_ACC_(BH_CA_X2, "eb", "rb")
+      ".Lbhc_end%=:\n"
+      : [t1r] "=&v"(t1r), [t1i] "=&v"(t1i), [t2r] "=&v"(t2r), [t2i] "=&v"(t2i),
+        [r1r] "=&v"(r1r), [r1i] "=&v"(r1i), [r2r] "=&v"(r2r), [r2i] "=&v"(r2i),
+        [ea] "=&v"(ea), [ra] "=&v"(ra), [u] "=&v"(u), [eb] "+v"(eb), [rb] "+v"(rb),
+        [n] "+s"(n)
+      : [x] "v"(x), [xc] "s"(xc), [rc] "s"(rc)
+      : "s36", "s37", "s38", "s39", "s40", "s41", "s42", "s43", "s44", "s45", "s46", "s47",
+        "s48", "s49", "s50", "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58", "s59",
+        "s60", "s61", "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71",
+        "s72", "s73", "s74", "s75", "s76", "s77", "s78", "s79", "s80", "s81", "s82", "s83",
+        "s84", "s85", "s86", "scc", "memory");
+}
+#undef BH_CA_ACC_
+#undef BH_CA_STEP_
+#endif
+
 // Partial sums of one wave over the classes of its p-groups: plist holds
 // [count, p_1, ..., p_count] (a wave's share of the longest-first split).
 //
@@ -151,7 +292,9 @@ struct Acc {
 // loads (one wait per round: scalar loads return out of order, so a wait
 // drains them all); (ea, ra) and (eb, rb) hold e, de/dx of two consecutive
 // degrees and each step overwrites the older pair, so no register moves are
-// needed.
+// needed.  Without Hessian terms and with wave-uniform weights the chain
+// runs as one asm block (chain_sums_asm) that also takes the peeled entry
+// into the first round and the tail into one last round.
 //
 // Class epilogue: with W1 = e^{-i p sigma} e^{-i q delta} and W2 =
 // e^{-i p sigma} e^{+i q delta} (advanced by e^{-+2i delta} per class), the
@@ -166,7 +309,7 @@ struct Acc {
 // written with the per-p sums A0 = sum (Re z1 + Re z2), A2 = sum q^2 (...),
 // B1 = sum q (Re z1 - Re z2); the mixed beta terms m Im(W1 r1) + n Im(W2 r2)
 // (and swapped) through ZP, ZQ as SP, SQ; d2/dbeta2 = Re(W1 q1 + W2 q2).
-template <bool HESS>
+template <bool HESS, bool XU = true>
 BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, int L,
                            const int32_t* __restrict__ p_first,
                            const double* __restrict__ rec, const double* __restrict__ X) {
@@ -243,56 +386,64 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
         eb = cp * sq;
         rb = eb * fma(-qd, A.is2, pic2);
       }
-      double t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i, ea, ra;
-      double q1r = 0.0, q1i = 0.0, q2r = 0.0, q2i = 0.0, qa = 0.0;
+      double t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i;
+      double q1r = 0.0, q1i = 0.0, q2r = 0.0, q2i = 0.0;
+#if defined(__HIP_DEVICE_COMPILE__)
+      if constexpr (!HESS && XU) {
+        chain_sums_asm(Xc, Rc, rem + 1, A.x, eb, rb, t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i);
+      } else
+#endif
       {
-        const double4 x0 = Xc[0];
-        const double2 c0_ = Rc[0];
-        t1r = x0.x * eb;
-        t1i = x0.y * eb;
-        t2r = x0.z * eb;
-        t2i = x0.w * eb;
-        r1r = x0.x * rb;
-        r1i = x0.y * rb;
-        r2r = x0.z * rb;
-        r2i = x0.w * rb;
-        const double u_ = c0_.x * (A.x - c0_.y);
-        ea = u_ * eb;
-        if constexpr (HESS) {
-          q1r = x0.x * qb;
-          q1i = x0.y * qb;
-          q2r = x0.z * qb;
-          q2i = x0.w * qb;
-          const double du_ = c0_.x * A.msb;
-          qa = fma(c0_.x * mx, eb, fma(du_ + du_, rb, u_ * qb));
-          ra = fma(du_, eb, u_ * rb);
-        } else {
-          ra = fma(c0_.x, eb, u_ * rb);
+        double ea, ra, qa = 0.0;
+        {
+          const double4 x0 = Xc[0];
+          const double2 c0_ = Rc[0];
+          t1r = x0.x * eb;
+          t1i = x0.y * eb;
+          t2r = x0.z * eb;
+          t2i = x0.w * eb;
+          r1r = x0.x * rb;
+          r1i = x0.y * rb;
+          r2r = x0.z * rb;
+          r2i = x0.w * rb;
+          const double u_ = c0_.x * (A.x - c0_.y);
+          ea = u_ * eb;
+          if constexpr (HESS) {
+            q1r = x0.x * qb;
+            q1i = x0.y * qb;
+            q2r = x0.z * qb;
+            q2i = x0.w * qb;
+            const double du_ = c0_.x * A.msb;
+            qa = fma(c0_.x * mx, eb, fma(du_ + du_, rb, u_ * qb));
+            ra = fma(du_, eb, u_ * rb);
+          } else {
+            ra = fma(c0_.x, eb, u_ * rb);
+          }
         }
-      }
-      // Full rounds of four entries: straight-line code, one load batch and
-      // one wait per round.  Then a tail of two and/or one entries.
-      const int n4 = rem & ~3;
-      int i = 1;
-      for (; i <= n4; i += 4) {
-        const double4 x0 = Xc[i], x1 = Xc[i + 1], x2 = Xc[i + 2], x3 = Xc[i + 3];
-        const double2 c0_ = Rc[i], c1 = Rc[i + 1], c2 = Rc[i + 2], c3 = Rc[i + 3];
-        BH_CHAIN_STEP(x0, c0_, ea, ra, qa, eb, rb, qb);
-        BH_CHAIN_STEP(x1, c1, eb, rb, qb, ea, ra, qa);
-        BH_CHAIN_STEP(x2, c2, ea, ra, qa, eb, rb, qb);
-        BH_CHAIN_STEP(x3, c3, eb, rb, qb, ea, ra, qa);
-      }
-      if (rem & 2) {
-        const double4 x0 = Xc[i], x1 = Xc[i + 1];
-        const double2 c0_ = Rc[i], c1 = Rc[i + 1];
-        BH_CHAIN_STEP(x0, c0_, ea, ra, qa, eb, rb, qb);
-        BH_CHAIN_STEP(x1, c1, eb, rb, qb, ea, ra, qa);
-        i += 2;
-      }
-      if (rem & 1) {
-        const double4 x0 = Xc[i];
-        const double2 c0_ = Rc[i];
-        BH_CHAIN_STEP(x0, c0_, ea, ra, qa, eb, rb, qb);
+        // Full rounds of four entries: straight-line code, one load batch and
+        // one wait per round.  Then a tail of two and/or one entries.
+        const int n4 = rem & ~3;
+        int i = 1;
+        for (; i <= n4; i += 4) {
+          const double4 x0 = Xc[i], x1 = Xc[i + 1], x2 = Xc[i + 2], x3 = Xc[i + 3];
+          const double2 c0_ = Rc[i], c1 = Rc[i + 1], c2 = Rc[i + 2], c3 = Rc[i + 3];
+          BH_CHAIN_STEP(x0, c0_, ea, ra, qa, eb, rb, qb);
+          BH_CHAIN_STEP(x1, c1, eb, rb, qb, ea, ra, qa);
+          BH_CHAIN_STEP(x2, c2, ea, ra, qa, eb, rb, qb);
+          BH_CHAIN_STEP(x3, c3, eb, rb, qb, ea, ra, qa);
+        }
+        if (rem & 2) {
+          const double4 x0 = Xc[i], x1 = Xc[i + 1];
+          const double2 c0_ = Rc[i], c1 = Rc[i + 1];
+          BH_CHAIN_STEP(x0, c0_, ea, ra, qa, eb, rb, qb);
+          BH_CHAIN_STEP(x1, c1, eb, rb, qb, ea, ra, qa);
+          i += 2;
+        }
+        if (rem & 1) {
+          const double4 x0 = Xc[i];
+          const double2 c0_ = Rc[i];
+          BH_CHAIN_STEP(x0, c0_, ea, ra, qa, eb, rb, qb);
+        }
       }
       if constexpr (HESS) {
         const double z1 = fma(W1.re, t1r, -W1.im * t1i);
