@@ -48,9 +48,18 @@ PEAK_HBM = 8.0e12              # bytes/s
 # de/dx' (2 FMA) = 24 flops; per class: seeds (4), the five 4-term
 # epilogue sums S, SP, D, SQ, gradient (33), the two phase rotations (12),
 # the power and q updates (2) = 51, less the 10 saved by the peeled first
-# entry (products instead of FMAs, no previous-degree term) = 41.
+# entry (products instead of FMAs, no previous-degree term) and the 8 of the
+# recurrence step after the chain's last entry (its degree is never used)
+# = 33; a class of one entry (m = L, 2L + 1 of them) has no step to drop
+# after its peeled entry, only its 6-flop update: 2 more.
 FLOP_PER_ENTRY = 24
-FLOP_PER_CLASS = 41
+FLOP_PER_CLASS = 33
+
+
+def band_flops(L: int) -> int:
+    """Algorithmic flops of one score + gradient evaluation at band L."""
+    ne, nc = band_counts(L)
+    return FLOP_PER_ENTRY * ne + FLOP_PER_CLASS * nc + 2 * (2 * L + 1)
 
 
 def band_counts(L: int):
@@ -314,8 +323,7 @@ def main():
     n_m, ms_m, _ = plan.profile_read("march_L*")
     flops_march = 0
     for L in w.bands:
-        ne, nc = band_counts(L)
-        flops_march += B * w.restarts * (w.steps + 1) * (FLOP_PER_ENTRY * ne + FLOP_PER_CLASS * nc)
+        flops_march += B * w.restarts * (w.steps + 1) * band_flops(L)
     launches_per_step = n_m / args.steps
     flops_per_launch = flops_march / launches_per_step
     avg_launch_s = (ms_m / n_m) / 1e3

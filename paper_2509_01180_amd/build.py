@@ -33,7 +33,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # the sine/cosine evaluations out of every loop and, short of registers,
 # spills them to scratch memory (112 bytes per lane in the ascent kernel,
 # whose stores reached HBM as hundreds of MB per launch); without it the
-# ascent kernel keeps one 8-byte value in scratch, stored once per wave.
+# ascent kernel needs no scratch.
 FILE_FLAGS: dict = {"bh_score.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
