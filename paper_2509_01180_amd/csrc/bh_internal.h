@@ -98,8 +98,10 @@ __device__ inline void parity_fold(float f[8]) {
   }
 }
 
-// The score loop loads table entries ahead of use; tables and per-particle
-// cross-power buffers carry this many zero entries past their end.
+// The score loop loads whole rounds of four table entries, up to three
+// past a chain's end; the recurrence tables and the per-particle cross-power
+// buffers carry this many entries past their end for the last chain (the
+// values read there are never used).
 constexpr int kTablePad = 4;
 
 // Largest restart count for which candidates can be pruned after the first
