@@ -44,6 +44,7 @@ struct Angles {
   cplx th1, th2;         // e^{-i delta}, e^{-2 i delta}, delta = (alpha - gamma) / 2
 };
 constexpr int kAngleWords = 13;   // doubles in Angles
+constexpr int kAngleMsb = 5;      // position of msb among them (store_angles)
 
 // Half-angle sines and cosines are kept at least this large in magnitude
 // (sign preserved) so that the x-derivative seeds below (up to 1 / s^4 for
@@ -187,92 +188,170 @@ struct Acc {
   "s_load_dwordx16 s[68:83], %[rc], s86\n"          \
   "s_waitcnt lgkmcnt(0)\n"
 
-__device__ inline void chain_sums_asm(const void* xc, const void* rc, int n, double x, double eb,
-                                      double rb, double& t1r, double& t1i, double& t2r,
-                                      double& t2i, double& r1r, double& r1i, double& r2r,
-                                      double& r2i) {
-  double ea, ra, u;
+// Chain text shared by the asm blocks below: the first round (peeled
+// entry, loaded by the block's own first loads) and the later rounds.
+#define BH_CA_CHAIN \
+  "v_mul_f64 %[t1r], s[36:37], %[eb]\n" \
+  "v_mul_f64 %[t1i], s[38:39], %[eb]\n" \
+  "v_mul_f64 %[t2r], s[40:41], %[eb]\n" \
+  "v_mul_f64 %[t2i], s[42:43], %[eb]\n" \
+  "v_mul_f64 %[r1r], s[36:37], %[rb]\n" \
+  "v_mul_f64 %[r1i], s[38:39], %[rb]\n" \
+  "v_mul_f64 %[r2r], s[40:41], %[rb]\n" \
+  "v_mul_f64 %[r2i], s[42:43], %[rb]\n" \
+  "s_cmp_eq_u32 %[n], 1\n" \
+  "s_cbranch_scc1 .Lbhc_end%=\n" \
+  "v_add_f64 %[u], %[x], -s[70:71]\n" \
+  "v_mul_f64 %[u], s[68:69], %[u]\n" \
+  "v_mul_f64 %[ea], %[u], %[eb]\n" \
+  "v_mul_f64 %[ra], %[u], %[rb]\n" \
+  "v_fmac_f64 %[ra], s[68:69], %[eb]\n" \
+  "s_cmp_eq_u32 %[n], 2\n" \
+  "s_cbranch_scc1 .Lbhc_f2%=\n" \
+  BH_CA_STEP_(BH_CA_E1, "ea", "ra", "eb", "rb") \
+  "s_cmp_eq_u32 %[n], 3\n" \
+  "s_cbranch_scc1 .Lbhc_f3%=\n" \
+  BH_CA_STEP_(BH_CA_E2, "eb", "rb", "ea", "ra") \
+  "s_cmp_eq_u32 %[n], 4\n" \
+  "s_cbranch_scc1 .Lbhc_f4%=\n" \
+  BH_CA_STEP_(BH_CA_E3, "ea", "ra", "eb", "rb") \
+  "s_sub_u32 %[n], %[n], 4\n" \
+  ".Lbhc_loop%=:\n" \
+  "s_add_u32 s84, s84, 0x80\n" \
+  "s_add_u32 s86, s86, 0x40\n" \
+  BH_CA_LOAD \
+  "s_cmp_le_i32 %[n], 4\n" \
+  "s_cbranch_scc1 .Lbhc_last%=\n" \
+  BH_CA_STEP_(BH_CA_E0, "eb", "rb", "ea", "ra") \
+  BH_CA_STEP_(BH_CA_E1, "ea", "ra", "eb", "rb") \
+  BH_CA_STEP_(BH_CA_E2, "eb", "rb", "ea", "ra") \
+  BH_CA_STEP_(BH_CA_E3, "ea", "ra", "eb", "rb") \
+  "s_sub_u32 %[n], %[n], 4\n" \
+  "s_branch .Lbhc_loop%=\n" \
+  ".Lbhc_last%=:\n" \
+  "s_cmp_eq_u32 %[n], 1\n" \
+  "s_cbranch_scc1 .Lbhc_l1%=\n" \
+  BH_CA_STEP_(BH_CA_E0, "eb", "rb", "ea", "ra") \
+  "s_cmp_eq_u32 %[n], 2\n" \
+  "s_cbranch_scc1 .Lbhc_l2%=\n" \
+  BH_CA_STEP_(BH_CA_E1, "ea", "ra", "eb", "rb") \
+  "s_cmp_eq_u32 %[n], 3\n" \
+  "s_cbranch_scc1 .Lbhc_l3%=\n" \
+  BH_CA_STEP_(BH_CA_E2, "eb", "rb", "ea", "ra") \
+  BH_CA_ACC_(BH_CA_X3, "ea", "ra") \
+  "s_branch .Lbhc_end%=\n" \
+  ".Lbhc_f2%=:\n" \
+  BH_CA_ACC_(BH_CA_X1, "ea", "ra") \
+  "s_branch .Lbhc_end%=\n" \
+  ".Lbhc_f3%=:\n" \
+  BH_CA_ACC_(BH_CA_X2, "eb", "rb") \
+  "s_branch .Lbhc_end%=\n" \
+  ".Lbhc_f4%=:\n" \
+  BH_CA_ACC_(BH_CA_X3, "ea", "ra") \
+  "s_branch .Lbhc_end%=\n" \
+  ".Lbhc_l1%=:\n" \
+  BH_CA_ACC_(BH_CA_X0, "eb", "rb") \
+  "s_branch .Lbhc_end%=\n" \
+  ".Lbhc_l2%=:\n" \
+  BH_CA_ACC_(BH_CA_X1, "ea", "ra") \
+  "s_branch .Lbhc_end%=\n" \
+  ".Lbhc_l3%=:\n" \
+  BH_CA_ACC_(BH_CA_X2, "eb", "rb") \
+  ".Lbhc_end%=:\n"
+
+// Class epilogue: the class's chain sums into the score, the alpha/gamma
+// sums SP, SQ of its p-group and the x-gradient, with the phase weights
+// W1, W2 of the class (the same fma sequence as the compiled epilogue).
+#define BH_CA_EPI_(D)                                \
+  "v_fmac_f64 %[S], %[w1r], %[t1r]\n"                \
+  "v_fma_f64 %[S], -%[w1i], %[t1i], %[S]\n"          \
+  "v_fmac_f64 %[S], %[w2r], %[t2r]\n"                \
+  "v_fma_f64 %[S], -%[w2i], %[t2i], %[S]\n"          \
+  "v_fmac_f64 %[SP], %[w1r], %[t1i]\n"               \
+  "v_fmac_f64 %[SP], %[w1i], %[t1r]\n"               \
+  "v_fmac_f64 %[SP], %[w2r], %[t2i]\n"               \
+  "v_fmac_f64 %[SP], %[w2i], %[t2r]\n"               \
+  "v_mul_f64 %[" D "], %[w1r], %[t1i]\n"                 \
+  "v_fmac_f64 %[" D "], %[w1i], %[t1r]\n"                \
+  "v_fma_f64 %[" D "], -%[w2r], %[t2i], %[" D "]\n"          \
+  "v_fma_f64 %[" D "], -%[w2i], %[t2r], %[" D "]\n"          \
+  "v_fmac_f64 %[SQ], %[qd], %[" D "]\n"                  \
+  "v_fmac_f64 %[gb], %[w1r], %[r1r]\n"               \
+  "v_fma_f64 %[gb], -%[w1i], %[r1i], %[gb]\n"        \
+  "v_fmac_f64 %[gb], %[w2r], %[r2r]\n"               \
+  "v_fma_f64 %[gb], -%[w2i], %[r2i], %[gb]\n"
+// The next class's W1 *= e^{-2i delta}, W2 *= e^{+2i delta}, s^q, q.
+#define BH_CA_ROT_(D)                                \
+  "v_mul_f64 %[" D "], %[w1i], %[th2i]\n"                \
+  "v_mul_f64 %[u], %[w1r], %[th2i]\n"                \
+  "v_fma_f64 %[w1r], %[w1r], %[th2r], -%[" D "]\n"       \
+  "v_fma_f64 %[w1i], %[w1i], %[th2r], %[u]\n"        \
+  "v_mul_f64 %[" D "], %[w2r], %[th2r]\n"                \
+  "v_mul_f64 %[u], %[w2r], %[th2i]\n"                \
+  "v_fma_f64 %[w2r], %[w2i], %[th2i], %[" D "]\n"        \
+  "v_fma_f64 %[w2i], %[w2i], %[th2r], -%[u]\n"       \
+  "v_mul_f64 %[sq], %[sq], %[s2]\n"                  \
+  "v_add_f64 %[qd], %[qd], 2.0\n"
+#define BH_CA_CLOBBERS                                                                     \
+  "s36", "s37", "s38", "s39", "s40", "s41", "s42", "s43", "s44", "s45", "s46", "s47", "s48", \
+      "s49", "s50", "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58", "s59", "s60",    \
+      "s61", "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72",    \
+      "s73", "s74", "s75", "s76", "s77", "s78", "s79", "s80", "s81", "s82", "s83", "s84",    \
+      "s85", "s86", "scc", "memory"
+
+// One class of a p-group as one asm block: the class's first-round loads
+// are issued first, and while they are in flight the previous class's
+// epilogue (if `prev`) and phase rotation run and this class's seeds
+// e_m = c^p s^q, de_m/dx = e_m (p / 4c^2 - q / 4s^2) are formed; then the
+// chain.  (t1r .. r2i): in, the previous class's chain sums; out, this
+// class's.  S, SP, SQ, gb accumulate; W1, W2, sq, qd advance to this class.
+__device__ inline void class_step_asm(int prev, const void* xc, const void* rc, int n, double x,
+                                      double th2r, double th2i, double s2, double is2,
+                                      double pic2, double cp, double& t1r, double& t1i,
+                                      double& t2r, double& t2i, double& r1r, double& r1i,
+                                      double& r2r, double& r2i, double& S, double& SP,
+                                      double& SQ, double& gb, double& w1r, double& w1i,
+                                      double& w2r, double& w2i, double& sq, double& qd) {
+  double ea, ra, u, eb, rb;   // ea also serves the epilogue
   asm volatile(
       "s_mov_b32 s84, 0\n"
       "s_mov_b32 s86, 0\n"
-      BH_CA_LOAD
-      "v_mul_f64 %[t1r], s[36:37], %[eb]\n"
-      "v_mul_f64 %[t1i], s[38:39], %[eb]\n"
-      "v_mul_f64 %[t2r], s[40:41], %[eb]\n"
-      "v_mul_f64 %[t2i], s[42:43], %[eb]\n"
-      "v_mul_f64 %[r1r], s[36:37], %[rb]\n"
-      "v_mul_f64 %[r1i], s[38:39], %[rb]\n"
-      "v_mul_f64 %[r2r], s[40:41], %[rb]\n"
-      "v_mul_f64 %[r2i], s[42:43], %[rb]\n"
-      "s_cmp_eq_u32 %[n], 1\n"
-      "s_cbranch_scc1 .Lbhc_end%=\n"
-      "v_add_f64 %[u], %[x], -s[70:71]\n"
-      "v_mul_f64 %[u], s[68:69], %[u]\n"
-      "v_mul_f64 %[ea], %[u], %[eb]\n"
-      "v_mul_f64 %[ra], %[u], %[rb]\n"
-      "v_fmac_f64 %[ra], s[68:69], %[eb]\n"
-      "s_cmp_eq_u32 %[n], 2\n"
-      "s_cbranch_scc1 .Lbhc_f2%=\n"
-      BH_CA_STEP_(BH_CA_E1, "ea", "ra", "eb", "rb")
-      "s_cmp_eq_u32 %[n], 3\n"
-      "s_cbranch_scc1 .Lbhc_f3%=\n"
-      BH_CA_STEP_(BH_CA_E2, "eb", "rb", "ea", "ra")
-      "s_cmp_eq_u32 %[n], 4\n"
-      "s_cbranch_scc1 .Lbhc_f4%=\n"
-      BH_CA_STEP_(BH_CA_E3, "ea", "ra", "eb", "rb")
-      "s_sub_u32 %[n], %[n], 4\n"
-      ".Lbhc_loop%=:\n"
-      "s_add_u32 s84, s84, 0x80\n"
-      "s_add_u32 s86, s86, 0x40\n"
-      BH_CA_LOAD
-      "s_cmp_le_i32 %[n], 4\n"
-      "s_cbranch_scc1 .Lbhc_last%=\n"
-      BH_CA_STEP_(BH_CA_E0, "eb", "rb", "ea", "ra")
-      BH_CA_STEP_(BH_CA_E1, "ea", "ra", "eb", "rb")
-      BH_CA_STEP_(BH_CA_E2, "eb", "rb", "ea", "ra")
-      BH_CA_STEP_(BH_CA_E3, "ea", "ra", "eb", "rb")
-      "s_sub_u32 %[n], %[n], 4\n"
-      "s_branch .Lbhc_loop%=\n"
-      ".Lbhc_last%=:\n"
-      "s_cmp_eq_u32 %[n], 1\n"
-      "s_cbranch_scc1 .Lbhc_l1%=\n"
-      BH_CA_STEP_(BH_CA_E0, "eb", "rb", "ea", "ra")
-      "s_cmp_eq_u32 %[n], 2\n"
-      "s_cbranch_scc1 .Lbhc_l2%=\n"
-      BH_CA_STEP_(BH_CA_E1, "ea", "ra", "eb", "rb")
-      "s_cmp_eq_u32 %[n], 3\n"
-      "s_cbranch_scc1 .Lbhc_l3%=\n"
-      BH_CA_STEP_(BH_CA_E2, "eb", "rb", "ea", "ra")
-      BH_CA_ACC_(BH_CA_X3, "ea", "ra")
-      "s_branch .Lbhc_end%=\n"
-      ".Lbhc_f2%=:\n"
-      BH_CA_ACC_(BH_CA_X1, "ea", "ra")
-      "s_branch .Lbhc_end%=\n"
-      ".Lbhc_f3%=:\n"
-      BH_CA_ACC_(BH_CA_X2, "eb", "rb")
-      "s_branch .Lbhc_end%=\n"
-      ".Lbhc_f4%=:\n"
-      BH_CA_ACC_(BH_CA_X3, "ea", "ra")
-      "s_branch .Lbhc_end%=\n"
-      ".Lbhc_l1%=:\n"
-      BH_CA_ACC_(BH_CA_X0, "eb", "rb")
-      "s_branch .Lbhc_end%=\n"
-      ".Lbhc_l2%=:\n"
-      BH_CA_ACC_(BH_CA_X1, "ea", "ra")
-      "s_branch .Lbhc_end%=\n"
-      ".Lbhc_l3%=:\n"
-      BH_CA_ACC_(BH_CA_X2, "eb", "rb")
-      ".Lbhc_end%=:\n"
-      : [t1r] "=&v"(t1r), [t1i] "=&v"(t1i), [t2r] "=&v"(t2r), [t2i] "=&v"(t2i),
-        [r1r] "=&v"(r1r), [r1i] "=&v"(r1i), [r2r] "=&v"(r2r), [r2i] "=&v"(r2i),
-        [ea] "=&v"(ea), [ra] "=&v"(ra), [u] "=&v"(u), [eb] "+v"(eb), [rb] "+v"(rb),
-        [n] "+s"(n)
-      : [x] "v"(x), [xc] "s"(xc), [rc] "s"(rc)
-      : "s36", "s37", "s38", "s39", "s40", "s41", "s42", "s43", "s44", "s45", "s46", "s47",
-        "s48", "s49", "s50", "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58", "s59",
-        "s60", "s61", "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71",
-        "s72", "s73", "s74", "s75", "s76", "s77", "s78", "s79", "s80", "s81", "s82", "s83",
-        "s84", "s85", "s86", "scc", "memory");
+      "s_add_u32 s85, s84, 0x40\n"
+      "s_load_dwordx16 s[36:51], %[xc], s84\n"
+      "s_load_dwordx16 s[52:67], %[xc], s85\n"
+      "s_load_dwordx16 s[68:83], %[rc], s86\n"
+      "s_cmp_eq_u32 %[prev], 0\n"
+      "s_cbranch_scc1 .Lbhc_seed%=\n"
+      BH_CA_EPI_("ea")
+      BH_CA_ROT_("ea")
+      ".Lbhc_seed%=:\n"
+      "v_mul_f64 %[eb], %[cp], %[sq]\n"
+      "v_fma_f64 %[rb], -%[qd], %[is2], %[pic2]\n"
+      "v_mul_f64 %[rb], %[eb], %[rb]\n"
+      "s_waitcnt lgkmcnt(0)\n"
+      BH_CA_CHAIN
+      : [t1r] "+v"(t1r), [t1i] "+v"(t1i), [t2r] "+v"(t2r), [t2i] "+v"(t2i), [r1r] "+v"(r1r),
+        [r1i] "+v"(r1i), [r2r] "+v"(r2r), [r2i] "+v"(r2i), [S] "+v"(S), [SP] "+v"(SP),
+        [SQ] "+v"(SQ), [gb] "+v"(gb), [w1r] "+v"(w1r), [w1i] "+v"(w1i), [w2r] "+v"(w2r),
+        [w2i] "+v"(w2i), [sq] "+v"(sq), [qd] "+v"(qd), [ea] "=&v"(ea), [ra] "=&v"(ra),
+        [u] "=&v"(u), [eb] "=&v"(eb), [rb] "=&v"(rb), [n] "+s"(n)
+      : [x] "v"(x), [th2r] "v"(th2r), [th2i] "v"(th2i), [s2] "v"(s2), [is2] "v"(is2),
+        [pic2] "v"(pic2), [cp] "v"(cp), [xc] "s"(xc), [rc] "s"(rc), [prev] "s"(prev)
+      : BH_CA_CLOBBERS);
+}
+
+// The last class's epilogue of a p-group.
+__device__ inline void class_epilogue_asm(double t1r, double t1i, double t2r, double t2i,
+                                          double r1r, double r1i, double r2r, double r2i,
+                                          double w1r, double w1i, double w2r, double w2i,
+                                          double qd, double& S, double& SP, double& SQ,
+                                          double& gb) {
+  double d;
+  asm volatile(BH_CA_EPI_("d")
+               : [S] "+v"(S), [SP] "+v"(SP), [SQ] "+v"(SQ), [gb] "+v"(gb), [d] "=&v"(d)
+               : [t1r] "v"(t1r), [t1i] "v"(t1i), [t2r] "v"(t2r), [t2i] "v"(t2i),
+                 [r1r] "v"(r1r), [r1i] "v"(r1i), [r2r] "v"(r2r), [r2i] "v"(r2i),
+                 [w1r] "v"(w1r), [w1i] "v"(w1i), [w2r] "v"(w2r), [w2i] "v"(w2i), [qd] "v"(qd));
 }
 #undef BH_CA_ACC_
 #undef BH_CA_STEP_
@@ -309,7 +388,10 @@ __device__ inline void chain_sums_asm(const void* xc, const void* rc, int n, dou
 // written with the per-p sums A0 = sum (Re z1 + Re z2), A2 = sum q^2 (...),
 // B1 = sum q (Re z1 - Re z2); the mixed beta terms m Im(W1 r1) + n Im(W2 r2)
 // (and swapped) through ZP, ZQ as SP, SQ; d2/dbeta2 = Re(W1 q1 + W2 q2).
-template <bool HESS, bool XU = true>
+// Without MSB (and HESS) the x-gradient sum is returned unscaled, for a
+// caller that applies -sin(beta) itself (from memory it reads afterwards,
+// rather than holding it in a register through the evaluation).
+template <bool HESS, bool XU = true, bool MSB = true>
 BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, int L,
                            const int32_t* __restrict__ p_first,
                            const double* __restrict__ rec, const double* __restrict__ X) {
@@ -365,6 +447,27 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
     double A0 = 0.0, A2 = 0.0, B1 = 0.0, ZP = 0.0, ZQ = 0.0;
     // HESS: s^{q-2} .. s^{q+2} (as cw), advanced by two per class
     double sw[5] = {0.0, q0 ? 1.0 : 0.0, q0 ? A.s : 1.0, q0 ? s2 : A.s, q0 ? s2 * A.s : s2};
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (!HESS && XU) {
+      // the classes of the p-group as asm blocks, each running the previous
+      // class's epilogue while its own first loads are in flight
+      double t1r = 0.0, t1i = 0.0, t2r = 0.0, t2i = 0.0, r1r = 0.0, r1i = 0.0, r2r = 0.0,
+             r2i = 0.0;
+      double w1r = W1.re, w1i = W1.im, w2r = W2.re, w2i = W2.im;
+      int prev = 0;
+      for (int q = q0; q <= 2 * L - p; q += 2) {
+        const int n = L - ((p + q) >> 1) + 1;
+        class_step_asm(prev, reinterpret_cast<const double4*>(X) + off,
+                       reinterpret_cast<const double2*>(rec) + off, n, A.x, A.th2.re, A.th2.im,
+                       s2, A.is2, pic2, cp, t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i, acc.S, SP,
+                       SQ, acc.gb, w1r, w1i, w2r, w2i, sq, qd);
+        prev = 1;
+        off += n;
+      }
+      class_epilogue_asm(t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i, w1r, w1i, w2r, w2i, qd, acc.S,
+                         SP, SQ, acc.gb);
+    } else
+#endif
     for (int q = q0; q <= 2 * L - p; q += 2) {
       const int m = (p + q) >> 1;
       const int rem = L - m;          // chain entries after the first
@@ -388,11 +491,6 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
       }
       double t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i;
       double q1r = 0.0, q1i = 0.0, q2r = 0.0, q2i = 0.0;
-#if defined(__HIP_DEVICE_COMPILE__)
-      if constexpr (!HESS && XU) {
-        chain_sums_asm(Xc, Rc, rem + 1, A.x, eb, rb, t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i);
-      } else
-#endif
       {
         double ea, ra, qa = 0.0;
         {
@@ -510,7 +608,7 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
     acc.hab = zpx;
     acc.hbg = zgx;
     acc.hbb = qsum;
-  } else {
+  } else if constexpr (MSB) {
     acc.gb *= A.msb;
   }
   return acc;

@@ -450,8 +450,9 @@ __global__ __launch_bounds__(64 * W) BH_MARCH_OCCUPANCY(NEWTON, G < 64) void k_m
     __syncthreads();
     for (int t = 0; t <= steps; ++t) {
       const Angles A = load_angles(ang + lane, 64);
-      const Acc mine =
-          eval_wave<NEWTON, G == 64>(A, wave_p + wave * (2 * L + 2), L, p_first, rec, Xp);
+      Acc mine =
+          eval_wave<NEWTON, G == 64, NEWTON>(A, wave_p + wave * (2 * L + 2), L, p_first, rec, Xp);
+      if constexpr (!NEWTON) mine.gb *= ang[kAngleMsb * 64 + lane];   // -sin(beta), trial point
       store_partials<NV>(mine, red, wave, lane);
       __syncthreads();
       if (wave == 0) {
