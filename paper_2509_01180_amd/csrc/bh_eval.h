@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "bh_special.h"
+#include "bh_tables.h"
 
 // Phases e^{-i p sigma} by FP64 sincos per p-group (1) or by a running
 // product along the wave's ascending p-list (0); build-time parameter.  The
@@ -462,7 +463,7 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
                        s2, A.is2, pic2, cp, t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i, acc.S, SP,
                        SQ, acc.gb, w1r, w1i, w2r, w2i, sq, qd);
         prev = 1;
-        off += n;
+        off += class_span(n);
       }
       class_epilogue_asm(t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i, w1r, w1i, w2r, w2i, qd, acc.S,
                          SP, SQ, acc.gb);
@@ -578,7 +579,7 @@ BH_HD inline Acc eval_wave(const Angles& A, const int32_t* __restrict__ plist, i
       acc.gb = fma(-W1.im, r1i, acc.gb);
       acc.gb = fma(W2.re, r2r, acc.gb);
       acc.gb = fma(-W2.im, r2i, acc.gb);
-      off += rem + 1;
+      off += class_span(rem + 1);
       W1 = cmul(W1, A.th2);
       W2 = cmul(W2, th2c);
       sq *= s2;
@@ -672,7 +673,7 @@ struct XRing {
     ++issued;
     if (4 * ++ik < in) return;
     ik = 0;
-    ioff += in;
+    ioff += class_span(in);
     iq += 2;
     if (iq > 2 * L - ip) {
       if (++ij >= np) return;
@@ -860,7 +861,7 @@ __device__ inline Acc eval_wave_staged(const Angles& A, const int32_t* __restric
       acc.gb = fma(-W1.im, r1i, acc.gb);
       acc.gb = fma(W2.re, r2r, acc.gb);
       acc.gb = fma(-W2.im, r2i, acc.gb);
-      off += n;
+      off += class_span(n);
       W1 = cmul(W1, A.th2);
       W2 = cmul(W2, th2c);
       qd += 2.0;

@@ -196,18 +196,19 @@ BandTables band_tables(int L, int Lmax) {
         ap[i] = A * nu[i] / nu[i + 1];
         bq[i] = B;
       }
-      for (int i = 0; i < len; ++i) {
-        const int l = m + i;
-        t.rec.push_back(ap[i]);
-        t.rec.push_back(bq[i]);
+      for (int i = 0; i < class_span(len); ++i) {
+        const bool pad = i >= len;
+        const int l = pad ? L : m + i;
+        t.rec.push_back(pad ? 0.0 : ap[i]);
+        t.rec.push_back(pad ? 0.0 : bq[i]);
         t.sel.push_back(l);
         t.sel.push_back(m);
         t.sel.push_back(n);
         t.sel.push_back(0);
-        t.wt.push_back(w1 * nu[i]);
-        t.wt.push_back(w2 * sgn_swap * nu[i]);
+        t.wt.push_back(pad ? 0.0 : w1 * nu[i]);
+        t.wt.push_back(pad ? 0.0 : w2 * sgn_swap * nu[i]);
       }
-      t.n_entries += len;
+      t.n_entries += class_span(len);
       t.n_classes += 1;
     }
   }
@@ -217,7 +218,8 @@ BandTables band_tables(int L, int Lmax) {
   // recurrence entries and class epilogues, in instructions of the kernel.
   std::vector<std::pair<int64_t, int>> cost;
   for (int p = 0; p <= 2 * L; ++p) {
-    const int64_t entries = t.p_first[p + 1] - t.p_first[p];
+    int64_t entries = 0;   // chain entries, padding not counted
+    for (int q = p % 2; q <= 2 * L - p; q += 2) entries += L - (p + q) / 2 + 1;
     const int64_t classes = (2 * L - p) / 2 + 1;
     cost.push_back({13 * entries + 32 * classes, p});
   }

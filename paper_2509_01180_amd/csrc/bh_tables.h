@@ -65,8 +65,17 @@ int column_parity_class(int l, int j);
 //              xi^l_{nm}.  w1 = w2 = 2 for m > |n| (the swapped pair and the
 //              conjugate pairs), w1 = 2, w2 = 0 for n = m > 0, w1 = w2 = 1 for
 //              n = -m < 0, w1 = 1, w2 = 0 for (0, 0).
-// Per class: a contiguous run of entries (L - m + 1 of them).
+// Per class: a contiguous run of entries (L - m + 1 of them), followed by
+// zero-weight padding entries up to a multiple of four (class_span), so that
+// every chain starts on a 128-byte boundary of the per-particle weights and
+// a 64-byte boundary of rec: the score kernels read a chain in 64-byte
+// scalar loads of four entries.  Padding entries repeat the class's last
+// (l, m, n) with zero weights and zero recurrence coefficients; no kernel
+// uses their values.
 // ---------------------------------------------------------------------------
+// Stored entries of a chain of n entries (n rounded up to a multiple of 4).
+constexpr int class_span(int n) { return (n + 3) & ~3; }
+
 struct BandTables {
   int L = -1;
   int n_classes = 0;

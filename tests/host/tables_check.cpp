@@ -47,8 +47,10 @@ static void check_index_set(int L) {
 
 static void check_band(int L, int Lmax) {
   const BandTables t = band_tables(L, Lmax);
+  // (2m + 1) classes of L - m + 1 chain entries each, stored padded to a
+  // multiple of four
   int64_t entries = 0;
-  for (int m = 0; m <= L; ++m) entries += (int64_t)(2 * m + 1) * (L - m + 1);
+  for (int m = 0; m <= L; ++m) entries += (int64_t)(2 * m + 1) * class_span(L - m + 1);
   CHECK(t.n_entries == entries, "band %d: %lld entries, expected %lld", L, (long long)t.n_entries,
         (long long)entries);
   CHECK(t.n_classes == (L + 1) * (L + 1), "band %d: %d classes", L, t.n_classes);
@@ -61,7 +63,24 @@ static void check_band(int L, int Lmax) {
   for (int p = 0; p <= 2 * L; ++p) {
     // classes of p: q = p mod 2, ..., 2L - p; class (m, n) holds l = m..L
     int64_t want = 0;
-    for (int q = p % 2; q <= 2 * L - p; q += 2) want += L - (p + q) / 2 + 1;
+    for (int q = p % 2; q <= 2 * L - p; q += 2) {
+      const int n = L - (p + q) / 2 + 1;
+      const int64_t e0 = t.p_first[p] + want;
+      CHECK(e0 % 4 == 0, "band %d: class (p %d, q %d) starts at entry %lld", L, p, q, (long long)e0);
+      // the chain's entries run l = m .. L, then padding with zero weights
+      for (int i = 0; i < class_span(n) && e0 + i < t.n_entries; ++i) {
+        const int64_t e = e0 + i;
+        if (i < n) {
+          CHECK(t.sel[4 * e] == (p + q) / 2 + i, "band %d: entry %lld degree", L, (long long)e);
+          CHECK(t.wt[2 * e] != 0.0, "band %d: entry %lld zero weight", L, (long long)e);
+        } else {
+          CHECK(t.wt[2 * e] == 0.0 && t.wt[2 * e + 1] == 0.0 && t.rec[2 * e] == 0.0 &&
+                    t.rec[2 * e + 1] == 0.0,
+                "band %d: padding entry %lld not zero", L, (long long)e);
+        }
+      }
+      want += class_span(n);
+    }
     CHECK(t.p_first[p + 1] - t.p_first[p] == want, "band %d: p-group %d size", L, p);
   }
   for (int64_t e = 0; e < t.n_entries; ++e) {
