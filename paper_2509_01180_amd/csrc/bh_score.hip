@@ -199,10 +199,10 @@ __global__ __launch_bounds__(512) void k_xi_band(
   for (int64_t e = tid; e < n_entries; e += blockDim.x) {
     const int l = sel[4 * e], m = sel[4 * e + 1], n = sel[4 * e + 2];
     const double w1 = wt[2 * e], w2 = wt[2 * e + 1];
+    // a chain's padding entries (zero weights) are never read: not written
+    if (w1 == 0.0 && w2 == 0.0) continue;
     double x1r = 0, x1i = 0, x2r = 0, x2i = 0;
-    // (a chain's padding entries have zero weights: their sums are skipped)
-    const int i_end = (w1 == 0.0 && w2 == 0.0) ? deg_start[l] : deg_start[l + 1];
-    for (int i = deg_start[l]; i < i_end; ++i) {
+    for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
       const int o = deg_off[i];
       const float2 bm = b[o + l + m], bn = b[o + l + n], am = sa[o + l + m], an = sa[o + l + n];
       const double bmr = bm.x, bmi = bm.y, bnr = bn.x, bni = bn.y;
