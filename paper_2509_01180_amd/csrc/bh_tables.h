@@ -65,16 +65,19 @@ int column_parity_class(int l, int j);
 //              xi^l_{nm}.  w1 = w2 = 2 for m > |n| (the swapped pair and the
 //              conjugate pairs), w1 = 2, w2 = 0 for n = m > 0, w1 = w2 = 1 for
 //              n = -m < 0, w1 = 1, w2 = 0 for (0, 0).
-// Per class: a contiguous run of entries (L - m + 1 of them), followed by
-// zero-weight padding entries up to a multiple of four (class_span), so that
-// every chain starts on a 128-byte boundary of the per-particle weights and
-// a 64-byte boundary of rec: the score kernels read a chain in 64-byte
-// scalar loads of four entries.  Padding entries repeat the class's last
-// (l, m, n) with zero weights and zero recurrence coefficients; no kernel
-// uses their values.
+// Per class: a contiguous run of entries (L - m + 1 of them), followed by a
+// zero-weight padding entry if that number is odd (class_span), so that
+// every chain starts on a 64-byte boundary of the per-particle weights: the
+// score kernels read a chain in rounds of four entries with 64-byte scalar
+// loads, and an aligned round's weights then span two cache lines rather
+// than three.  (Padding to four entries, which also aligns rec, measured the
+// same for the ascent kernel and cost the Newton bands, which stream the
+// weights from HBM, 13 % more bytes instead of 6 %.)  Padding entries repeat
+// the class's last (l, m, n) with zero weights and zero recurrence
+// coefficients; no kernel uses their values.
 // ---------------------------------------------------------------------------
-// Stored entries of a chain of n entries (n rounded up to a multiple of 4).
-constexpr int class_span(int n) { return (n + 3) & ~3; }
+// Stored entries of a chain of n entries (n rounded up to even).
+constexpr int class_span(int n) { return (n + 1) & ~1; }
 
 struct BandTables {
   int L = -1;

@@ -47,8 +47,8 @@ static void check_index_set(int L) {
 
 static void check_band(int L, int Lmax) {
   const BandTables t = band_tables(L, Lmax);
-  // (2m + 1) classes of L - m + 1 chain entries each, stored padded to a
-  // multiple of four
+  // (2m + 1) classes of L - m + 1 chain entries each, stored padded to an
+  // even number
   int64_t entries = 0;
   for (int m = 0; m <= L; ++m) entries += (int64_t)(2 * m + 1) * class_span(L - m + 1);
   CHECK(t.n_entries == entries, "band %d: %lld entries, expected %lld", L, (long long)t.n_entries,
@@ -66,7 +66,7 @@ static void check_band(int L, int Lmax) {
     for (int q = p % 2; q <= 2 * L - p; q += 2) {
       const int n = L - (p + q) / 2 + 1;
       const int64_t e0 = t.p_first[p] + want;
-      CHECK(e0 % 4 == 0, "band %d: class (p %d, q %d) starts at entry %lld", L, p, q, (long long)e0);
+      CHECK(e0 % 2 == 0, "band %d: class (p %d, q %d) starts at entry %lld", L, p, q, (long long)e0);
       // the chain's entries run l = m .. L, then padding with zero weights
       for (int i = 0; i < class_span(n) && e0 + i < t.n_entries; ++i) {
         const int64_t e = e0 + i;
