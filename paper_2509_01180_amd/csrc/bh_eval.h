@@ -788,10 +788,14 @@ __device__ inline Acc eval_wave_staged(const Angles& A, const int32_t* __restric
                           (qd * (pd + 1.0) + pd * (qd + 1.0)) * eb);
       double t1r, t1i, t2r, t2i, r1r, r1i, r2r, r2i, ea, ra, qa;
       double q1r, q1i, q2r, q2i;
+      // A block's four recurrence entries are loaded before its ring reads,
+      // whose wait then covers them too (one wait per block, not one per
+      // entry); the last block's loads may read past the chain (padding).
+      double2 rc0 = Rc[0], rc1 = Rc[1], rc2 = Rc[2], rc3 = Rc[3];
       Block4 xb = ring_block(xr.next(), gq);
       {
         const double4 x0 = xb.x[0];
-        const double2 c0_ = Rc[0];
+        const double2 c0_ = rc0;
         t1r = x0.x * eb;
         t1i = x0.y * eb;
         t2r = x0.z * eb;
@@ -812,25 +816,25 @@ __device__ inline Acc eval_wave_staged(const Angles& A, const int32_t* __restric
       }
       for (int i0 = 0; i0 < n; i0 += 4) {
         if (i0 > 0) {
+          rc0 = Rc[i0];
+          rc1 = Rc[i0 + 1];
+          rc2 = Rc[i0 + 2];
+          rc3 = Rc[i0 + 3];
           xb = ring_block(xr.next(), gq);
           const double4 x0 = xb.x[0];
-          const double2 c0_ = Rc[i0];
-          BH_CHAIN_STEP(x0, c0_, eb, rb, qb, ea, ra, qa);
+          BH_CHAIN_STEP(x0, rc0, eb, rb, qb, ea, ra, qa);
         }
         if (i0 + 1 < n) {
           const double4 x1 = xb.x[1];
-          const double2 c1 = Rc[i0 + 1];
-          BH_CHAIN_STEP(x1, c1, ea, ra, qa, eb, rb, qb);
+          BH_CHAIN_STEP(x1, rc1, ea, ra, qa, eb, rb, qb);
         }
         if (i0 + 2 < n) {
           const double4 x2 = xb.x[2];
-          const double2 c2 = Rc[i0 + 2];
-          BH_CHAIN_STEP(x2, c2, eb, rb, qb, ea, ra, qa);
+          BH_CHAIN_STEP(x2, rc2, eb, rb, qb, ea, ra, qa);
         }
         if (i0 + 3 < n) {
           const double4 x3 = xb.x[3];
-          const double2 c3 = Rc[i0 + 3];
-          BH_CHAIN_STEP(x3, c3, ea, ra, qa, eb, rb, qb);
+          BH_CHAIN_STEP(x3, rc3, ea, ra, qa, eb, rb, qb);
         }
       }
       const double z1 = fma(W1.re, t1r, -W1.im * t1i);
