@@ -693,7 +693,7 @@ def serving_run(S: ServingSetup, boxes, method: str, rate: float, duration: floa
     from GPU event timestamps), accuracy against the planted rotations."""
     import torch
     import synth.serving as ss
-    from paper_2509_01180_amd.serving import Engine, Request, latency_summary
+    from paper_2509_01180_amd.serving import Engine, Request, Rows, latency_summary
     dev, P, pool = S.dev, S.P, S.pool
     if method == "paper" and band_thresholds is None:
         boxes_cfg = {N: (SERVE_PLANS[N][0], SERVE_PAPER_BANDS[N]) for N in boxes}
@@ -710,8 +710,9 @@ def serving_run(S: ServingSetup, boxes, method: str, rate: float, duration: floa
         N, t, n = spec.box, spec.template, spec.n
 
         def volumes():
+            # rows of the resident pool, read in place by the expansion
             j = (spec.offset + torch.arange(n, device=dev)) % pool + t * pool
-            return S.pools[N].index_select(0, j)
+            return Rows(S.pools[N], j)
 
         def starts():
             k = (spec.start_offset + torch.arange(n, device=dev)) % S.start_pool.shape[0]

@@ -113,7 +113,8 @@ int64_t bh_plan_num_coeffs(const bh_plan* p, int L);
 /* Synchronise `stream`, then report errors that the plan's kernels found in
  * device-side arguments since the last report: BH_EINVAL if a particle's
  * template index (bh_align_t, bh_align_uneven) was outside the template
- * table, else BH_OK.  Reporting clears the flag.  The flag lives in pinned
+ * table or a volume row (bh_expand_rows) outside the volume stack, else
+ * BH_OK.  Reporting clears the flag.  The flag lives in pinned
  * host memory that the kernels write, so bh_align_t and bh_align_uneven
  * also return it at entry (enqueuing nothing) once the offending call's
  * kernels have run. */
@@ -152,6 +153,20 @@ int bh_expand_ex(bh_plan* p, const float* vols, int64_t B, int mode, float* coef
  * particles of several plans can share one coefficient array. */
 int bh_expand_into(bh_plan* p, const float* vols, int64_t B, int mode, float* coeffs, int64_t ldc,
                    float* coarse, void* stream);
+
+/* Expansion (Sec. II-A) of volumes picked by row from a resident stack,
+ * read in place: particle b is volume rows[b] of vols.
+ * vols:   dev float[n_vols][N][N][N]
+ * rows:   dev int64[B], each in 0..n_vols-1 (repeats allowed)
+ * coeffs, ldc, coarse, mode: as bh_expand_into (ldc == 0: C(L_max)).
+ * The result for particle b is bit-identical to bh_expand_into on a copy
+ * of vols[rows[b]] at position b (same mode, same B).  A row outside
+ * 0..n_vols-1 is not read: that particle's coefficients have NaN real
+ * parts (the imaginary parts of m = 0 coefficients stay 0) and the
+ * plan's error word is raised, which bh_plan_check (and the next
+ * bh_align_t or bh_align_uneven on the plan) reports as BH_EINVAL. */
+int bh_expand_rows(bh_plan* p, const float* vols, int64_t n_vols, const int64_t* rows, int64_t B,
+                   int mode, float* coeffs, int64_t ldc, float* coarse, void* stream);
 
 /* ---------------------------------------------------------------------
  * Allocation-free expansion, for callers that cannot allocate device memory

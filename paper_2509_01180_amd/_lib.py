@@ -78,6 +78,7 @@ SIGNATURES = {
     "bh_prune_candidates": (_I, [_P, _P, _P, _I64, _I, _I, ctypes.c_double, _P, _P, _P]),
     "bh_align_shifts": (_I, [_P, _P, _I64, _P, _I, _P, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P]),
     "bh_expand_into": (_I, [_P, _P, _I64, _I, _P, _I64, _P, _P]),
+    "bh_expand_rows": (_I, [_P, _P, _I64, _P, _I64, _I, _P, _I64, _P, _P]),
     "bh_align_uneven": (_I, [_P, _P, _I64, _P, _P, _I64, _I, _P, _I64, ctypes.POINTER(AlignOpts),
                              _P, _P, _P, _P, _P, _P]),
     "bh_align_t": (_I, [_P, _P, _P, _I, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),

@@ -116,8 +116,9 @@ class Plan:
 
     def check(self) -> None:
         """Synchronise the current stream and raise BhError (BH_EINVAL) if a
-        kernel of this plan met a template index outside its table since the
-        last check (see bh_plan_check)."""
+        kernel of this plan met a template index outside its table or a
+        volume row outside its stack since the last check (see
+        bh_plan_check)."""
         check(lib().bh_plan_check(self._h, _stream()), "bh_plan_check")
 
     def num_coeffs(self, L: int) -> int:
@@ -237,6 +238,30 @@ class Plan:
             _dev(coarse, torch.float32, (B, ldc, 2), "coarse")
         check(lib().bh_expand_into(self._h, _ptr(vols), B, code, _ptr(out), ldc, _ptr(coarse),
                                    _stream()), "bh_expand_into")
+        return out
+
+    def expand_rows(self, vols: torch.Tensor, rows: torch.Tensor, mode: str = "fp32",
+                    out: torch.Tensor | None = None, coarse: torch.Tensor | None = None,
+                    batch_invariant: bool = False) -> torch.Tensor:
+        """Expansion of the volumes vols[rows[b]] read in place from a
+        resident stack vols [n, N, N, N] float32 (see bh_expand_rows); rows
+        is an int64 device tensor [B].  out (and coarse, mode "bf16x3")
+        [B, ldc, 2] float32 with ldc >= C; the same bits as expand_into on
+        vols[rows]."""
+        modes = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+        code = modes[mode] | (BH_EXPAND_BATCH_INVARIANT if batch_invariant else 0)
+        n = vols.shape[0]
+        _dev(vols, torch.float32, (n, self.N, self.N, self.N), "vols")
+        B = rows.shape[0] if rows.dim() == 1 else -1
+        _dev(rows, torch.int64, (B,), "rows")
+        if out is None:
+            out = torch.empty((B, self.C, 2), dtype=torch.float32, device=vols.device)
+        ldc = out.shape[1]
+        _dev(out, torch.float32, (B, ldc, 2), "out")
+        if coarse is not None:
+            _dev(coarse, torch.float32, (B, ldc, 2), "coarse")
+        check(lib().bh_expand_rows(self._h, _ptr(vols), n, _ptr(rows), B, code, _ptr(out), ldc,
+                                   _ptr(coarse), _stream()), "bh_expand_rows")
         return out
 
     def align_uneven(self, a: torch.Tensor, Lp, templates: torch.Tensor,

@@ -156,13 +156,14 @@ int get_band(bh_plan* p, int L, const DevBand** out) {
 }
 
 // BH_EINVAL (and the flag cleared) if a kernel of an earlier call on this
-// plan met a template index outside its table.
+// plan met a template index outside its table or a volume row outside its
+// stack.
 int take_pending_error(bh_plan* p) {
   if (p->err_host && __atomic_exchange_n(p->err_host, 0, __ATOMIC_ACQ_REL) != 0)
     return set_error(BH_EINVAL,
                      "an earlier call on this plan had a template index outside "
-                     "0..n_templates-1; the scores, step scales and energies of those particles "
-                     "are NaN");
+                     "0..n_templates-1 or a volume row outside 0..n_vols-1; the results of "
+                     "those particles are NaN");
   return BH_OK;
 }
 
@@ -466,6 +467,33 @@ int bh_expand_into(bh_plan* p, const float* vols, int64_t B, int mode, float* co
       return launch_expand(p, vols, B, coeffs, (hipStream_t)stream, invariant, nullptr, 1, ldc);
     return launch_expand_bf16(p, vols, B, mode == BH_EXPAND_BF16X3, coeffs, coarse,
                               (hipStream_t)stream, invariant, ldc);
+  });
+}
+
+int bh_expand_rows(bh_plan* p, const float* vols, int64_t n_vols, const int64_t* rows, int64_t B,
+                   int mode, float* coeffs, int64_t ldc, float* coarse, void* stream) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (B < 0 || B > (1LL << 21)) return set_error(BH_EINVAL, "batch size out of range");
+  if (n_vols < 0 || n_vols > (1LL << 40) / ((int64_t)p->N * p->N * p->N))
+    return set_error(BH_EINVAL, "volume count out of range");
+  if (ldc == 0) ldc = p->C;
+  if (ldc < p->C || ldc > (1LL << 24)) return set_error(BH_EINVAL, "ldc smaller than C(L_max)");
+  const bool invariant = (mode & BH_EXPAND_BATCH_INVARIANT) != 0;
+  mode &= ~BH_EXPAND_BATCH_INVARIANT;
+  if (mode != BH_EXPAND_FP32 && mode != BH_EXPAND_BF16 && mode != BH_EXPAND_BF16X3)
+    return set_error(BH_EINVAL, "unknown expansion mode");
+  if (coarse && mode != BH_EXPAND_BF16X3)
+    return set_error(BH_EINVAL, "a coarse output needs the BF16X3 mode");
+  if (B == 0) return BH_OK;
+  if (!vols || !rows || !coeffs) return set_error(BH_EINVAL, "NULL buffer");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
+    if (mode == BH_EXPAND_FP32)
+      return launch_expand(p, vols, B, coeffs, (hipStream_t)stream, invariant, nullptr, 1, ldc,
+                           rows, n_vols);
+    return launch_expand_bf16(p, vols, B, mode == BH_EXPAND_BF16X3, coeffs, coarse,
+                              (hipStream_t)stream, invariant, ldc, rows, n_vols);
   });
 }
 

@@ -35,9 +35,13 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
 
 // Ft[P][v][b] = g_P of particle b at representative v (0 outside v < VR,
-// b < B).  32x32 LDS transpose per class.
+// b < B).  32x32 LDS transpose per class.  Particle b's volume is
+// vols[rows[b]] with a row table (a row outside [0, n_rows) reads as NaN
+// and raises the error word `bad`), else vols[b].
 __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ vols, int64_t vol_stride,
-                                                int64_t B, const int32_t* __restrict__ vrep,
+                                                int64_t B, const int64_t* __restrict__ rows,
+                                                int64_t n_rows, int* bad,
+                                                const int32_t* __restrict__ vrep,
                                                 int64_t VR, int64_t VR_pad, int64_t M_pad, int N,
                                                 float* __restrict__ Ft) {
   __shared__ float tile[kParityClasses][32][33];
@@ -50,10 +54,12 @@ __global__ __launch_bounds__(256) void k_gather(const float* __restrict__ vols, 
   for (int i = 0; i < 4; ++i) {
     const int64_t b = b0 + ty + 8 * i;
     float f[8];
-    const bool in = v < VR && b < B;
-    const float* vb = vols + (in ? b * vol_stride : 0);
+    const int64_t r = volume_row(rows, n_rows, B, b, v == 0 ? bad : nullptr);
+    const bool in = v < VR && r >= 0;
+    const float* vb = vols + (in ? r * vol_stride : 0);
+    const float outside = r == -2 ? __builtin_nanf("") : 0.0f;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) f[s] = in ? vb[off[s]] : 0.0f;
+    for (int s = 0; s < 8; ++s) f[s] = in ? vb[off[s]] : outside;
     parity_fold(f);
 #pragma unroll
     for (int c = 0; c < kParityClasses; ++c) tile[c][ty + 8 * i][tx] = f[c];
@@ -226,7 +232,8 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ part, 
 }  // namespace
 
 int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s,
-                  bool batch_invariant, const ShiftTable* shifts, int S, int64_t ldc) {
+                  bool batch_invariant, const ShiftTable* shifts, int S, int64_t ldc,
+                  const int64_t* rows, int64_t n_rows) {
   if (ldc <= 0) ldc = p->C;
   if (shifts) B *= S;   // one GEMM row per (particle, shift)
   if (B == 0) return BH_OK;
@@ -250,8 +257,8 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
   } else {
     ProfScope ps(p, "gather", s, B);
     hipLaunchKernelGGL(k_gather, dim3((unsigned)(p->VR_pad / 32), (unsigned)(M_pad / 32)),
-                       dim3(256), 0, s, vols, vol_stride, B, p->vrep, p->VR, p->VR_pad, M_pad,
-                       p->N, Ft);
+                       dim3(256), 0, s, vols, vol_stride, B, rows, n_rows, p->err_dev, p->vrep,
+                       p->VR, p->VR_pad, M_pad, p->N, Ft);
   }
   BH_HIP(hipGetLastError());
   {
@@ -332,8 +339,8 @@ int launch_expand_noalloc(bh_plan* p, const float* vols, int64_t B, float* coeff
     float* Ft = (float*)base;
     float* part = Ft + (size_t)kParityClasses * p->VR_pad * M_pad;
     hipLaunchKernelGGL(k_gather, dim3((unsigned)(p->VR_pad / 32), (unsigned)(M_pad / 32)),
-                       dim3(256), 0, s, vols + b0 * vol_stride, vol_stride, nb, p->vrep, p->VR,
-                       p->VR_pad, M_pad, p->N, Ft);
+                       dim3(256), 0, s, vols + b0 * vol_stride, vol_stride, nb, nullptr, 0,
+                       nullptr, p->vrep, p->VR, p->VR_pad, M_pad, p->N, Ft);
     BH_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)(mt * nt * nsplit)), dim3(256), 0, s, Ft,
                        p->psi, part, M_pad, p->C_pad, p->VR_pad, p->ctiles, (int)nk, nsplit);

@@ -62,9 +62,13 @@ __global__ __launch_bounds__(256) void k_psi_split(const float* __restrict__ psi
 }
 
 // Fh[P][b][v], Fl[P][b][v] = split of the class-P mirror sum of particle b
-// at representative v (0 outside v < VR, b < B).
+// at representative v (0 outside v < VR, b < B).  Particle b's volume is
+// vols[rows[b]] with a row table (a row outside [0, n_rows) reads as NaN
+// and raises the error word `bad`), else vols[b].
 __global__ __launch_bounds__(256) void k_gather_split(const float* __restrict__ vols,
                                                       int64_t vol_stride, int64_t B,
+                                                      const int64_t* __restrict__ rows,
+                                                      int64_t n_rows, int* bad,
                                                       const int32_t* __restrict__ vrep, int64_t VR,
                                                       int64_t VR_pad, int64_t M_pad, int N,
                                                       uint16_t* __restrict__ fh,
@@ -76,10 +80,12 @@ __global__ __launch_bounds__(256) void k_gather_split(const float* __restrict__ 
   const int64_t slab = M_pad * VR_pad;
   for (int64_t b = blockIdx.y; b < M_pad; b += gridDim.y) {
     float f[8];
-    const bool in = v < VR && b < B;
-    const float* vb = vols + (in ? b * vol_stride : 0);
+    const int64_t r = volume_row(rows, n_rows, B, b, v == 0 ? bad : nullptr);
+    const bool in = v < VR && r >= 0;
+    const float* vb = vols + (in ? r * vol_stride : 0);
+    const float outside = r == -2 ? __builtin_nanf("") : 0.0f;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) f[s] = in ? vb[off[s]] : 0.0f;
+    for (int s = 0; s < 8; ++s) f[s] = in ? vb[off[s]] : outside;
     parity_fold(f);
 #pragma unroll
     for (int c = 0; c < kParityClasses; ++c) {
@@ -288,7 +294,8 @@ int ensure_bf16_basis(bh_plan* p) {
 }
 
 int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, float* coeffs,
-                       float* coarse_out, hipStream_t s, bool batch_invariant, int64_t ldc) {
+                       float* coarse_out, hipStream_t s, bool batch_invariant, int64_t ldc,
+                       const int64_t* rows, int64_t n_rows) {
   if (ldc <= 0) ldc = p->C;
   if (B == 0) return BH_OK;
   int rc = ensure_bf16_basis(p);
@@ -311,7 +318,8 @@ int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, fl
     ProfScope ps(p, "gather_bf16", s, B);
     const unsigned gy = (unsigned)(M_pad < 4096 ? M_pad : 4096);
     hipLaunchKernelGGL(k_gather_split, dim3((unsigned)((p->VR_pad + 255) / 256), gy), dim3(256),
-                       0, s, vols, vol_stride, B, p->vrep, p->VR, p->VR_pad, M_pad, p->N, fh, fl);
+                       0, s, vols, vol_stride, B, rows, n_rows, p->err_dev, p->vrep, p->VR,
+                       p->VR_pad, M_pad, p->N, fh, fl);
   }
   BH_HIP(hipGetLastError());
   {

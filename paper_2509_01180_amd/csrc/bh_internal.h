@@ -83,6 +83,19 @@ __device__ inline void mirror_offsets(int32_t lin, int N, int32_t off[8]) {
   for (int s = 0; s < 8; ++s) off[s] = I[s & 1] + J[(s >> 1) & 1] + K[s >> 2];
 }
 
+// The volume row that expansion particle b reads: rows[b] with a row table,
+// else b; -1 for the padding particles b >= B; -2 (and the error word `bad`
+// raised, when given) for a table entry outside [0, n_rows).
+__device__ inline int64_t volume_row(const int64_t* __restrict__ rows, int64_t n_rows, int64_t B,
+                                     int64_t b, int* bad) {
+  if (b >= B) return -1;
+  if (!rows) return b;
+  const int64_t r = rows[b];
+  if (r >= 0 && r < n_rows) return r;
+  if (bad) *reinterpret_cast<volatile int*>(bad) = 1;
+  return -2;
+}
+
 // In place: f[P] = sum_s (-1)^popcount(P & s) f[s] (size-8 Walsh-Hadamard),
 // the mirror sum g_P of parity class P from the 8 image values.
 __device__ inline void parity_fold(float f[8]) {
@@ -220,9 +233,11 @@ struct ShiftTable {
 // With `shifts` the rows are the B*S shifted volumes (particle-major) of
 // the S integer voxel shifts.
 // ldc: complex stride between particles' coefficient rows (0: C(L_max)).
+// rows: device table of B volume rows (particle b is vols[rows[b]], vols
+// holding n_rows volumes), or NULL (particle b is vols[b]); not with shifts.
 int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s,
                   bool batch_invariant = false, const ShiftTable* shifts = nullptr, int S = 1,
-                  int64_t ldc = 0);
+                  int64_t ldc = 0, const int64_t* rows = nullptr, int64_t n_rows = 0);
 // Allocation-free expansion: resolve this device's copy of the static
 // scratch (once per device, with the device current; called at plan
 // creation), how many 128-particle tiles one pass holds (returns the split-K
@@ -232,7 +247,7 @@ int noalloc_expand_pass(const bh_plan* p, int64_t* tiles_per_pass);
 int launch_expand_noalloc(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipStream_t s);
 int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, float* coeffs,
                        float* coarse_out, hipStream_t s, bool batch_invariant = false,
-                       int64_t ldc = 0);
+                       int64_t ldc = 0, const int64_t* rows = nullptr, int64_t n_rows = 0);
 int launch_cross_power_dense(bh_plan* p, const DevBand& band, const float* a, const float* b,
                              int64_t B, double* xi, hipStream_t s);
 int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const float* b, int64_t B,

@@ -11,6 +11,8 @@ resident templates) queue on arrival and are served in ticks.  One tick:
    coarse bands and the refined, near-FP32 ones for the final band) and its
    starting rotations are loaded; from then on the cohort's coefficients
    and the restarts' angles (the optimiser state) stay on the device.
+   Requests that name rows of one resident volume stack (Rows) are expanded
+   from it in place; others are first copied into one cohort array.
 2. Marching.  Every live cohort advances by one band of the frequency march
    (Sec. II-C): the gradient-ascent steps of that band for all of its
    restarts, against each particle's own template.  Cohorts admitted at
@@ -52,11 +54,23 @@ class BoxSpec:
 
 
 @dataclass
+class Rows:
+    """A request's particles as rows of a resident volume stack: particle i
+    is stack[index[i]].  stack: [n_vols, N, N, N] float32 device tensor;
+    index: [n] int64 tensor (device, or host: then range-checked at
+    submission).  The expansion reads the rows in place; a device index
+    outside the stack gives NaN results for those particles and BhError
+    (BH_EINVAL) from the engine's next library call on that box edge."""
+    stack: object
+    index: object
+
+
+@dataclass
 class Request:
     """One alignment request.
 
-    volumes: [n, N, N, N] float32 device tensor, or a callable returning it
-             (called once, at admission).
+    volumes: [n, N, N, N] float32 device tensor, Rows, or a callable
+             returning either (called once, at admission).
     starts:  [n, P, 3] float64 device tensor of starting Euler triples, or a
              callable returning it.
     arrival: time.perf_counter() at submission (set by submit if None).
@@ -265,6 +279,8 @@ class Engine:
     def submit(self, req: Request) -> Request:
         if req.template < 0 or req.template >= self.templates[req.box].shape[0]:
             raise ValueError(f"template {req.template} is not resident for {req.box}^3")
+        if isinstance(req.volumes, Rows):
+            self._check_rows(req, req.volumes)
         if req.arrival is None:
             req.arrival = time.perf_counter()
         if req.rid < 0:
@@ -320,6 +336,55 @@ class Engine:
                 ev.synchronize()
         return out + self._collect(block=True)
 
+    def _check_rows(self, r: Request, v: Rows) -> None:
+        torch, N = self.torch, r.box
+        st, ix = v.stack, v.index
+        if (not isinstance(st, torch.Tensor) or not st.is_cuda or st.dtype != torch.float32
+                or st.dim() != 4 or tuple(st.shape[1:]) != (N, N, N) or not st.is_contiguous()):
+            raise ValueError(f"request {r.rid}: Rows.stack must be a contiguous "
+                             f"[n, {N}, {N}, {N}] float32 device tensor")
+        if isinstance(ix, torch.Tensor) and ix.is_cuda:
+            if ix.dtype != torch.int64 or tuple(ix.shape) != (r.n,):
+                raise ValueError(f"request {r.rid}: Rows.index must be [{r.n}] int64")
+            return
+        h = np.asarray(ix.cpu() if isinstance(ix, torch.Tensor) else ix)
+        if h.shape != (r.n,) or h.dtype.kind not in "iu":
+            raise ValueError(f"request {r.rid}: Rows.index must hold {r.n} integers")
+        if h.size and (h.min() < 0 or h.max() >= st.shape[0]):
+            raise ValueError(f"request {r.rid}: Rows.index outside 0..{st.shape[0] - 1}")
+
+    def _cohort_volumes(self, c: Cohort, s):
+        """The cohort's volumes on stream s: (stack, int64 row index) when
+        every request names rows of one stack (nothing is copied), else one
+        [n, N, N, N] tensor (the requests' volumes concatenated)."""
+        torch = self.torch
+        vols = [r.volumes() if callable(r.volumes) else r.volumes for r in c.requests]
+        rows = []
+        for r, v in zip(c.requests, vols):
+            if isinstance(v, Rows):
+                self._check_rows(r, v)
+                ix = v.index
+                if not (isinstance(ix, torch.Tensor) and ix.is_cuda):
+                    ix = torch.as_tensor(np.asarray(ix.cpu() if isinstance(ix, torch.Tensor)
+                                                    else ix, dtype=np.int64)).to(self.dev)
+                v = Rows(v.stack, ix.contiguous())
+                v.stack.record_stream(s)
+                v.index.record_stream(s)
+                rows.append(v)
+            else:
+                if tuple(v.shape) != (r.n, c.box, c.box, c.box) or v.dtype != torch.float32:
+                    raise ValueError(f"request {r.rid}: volumes must be [{r.n}, {c.box}^3] float32")
+                v.record_stream(s)
+                rows.append(v)
+        if all(isinstance(v, Rows) for v in rows):
+            st = rows[0].stack
+            if all(v.stack.data_ptr() == st.data_ptr() and v.stack.shape == st.shape
+                   for v in rows):
+                ix = rows[0].index if len(rows) == 1 else torch.cat([v.index for v in rows])
+                return st, ix
+        mats = [v.stack.index_select(0, v.index) if isinstance(v, Rows) else v for v in rows]
+        return (mats[0].contiguous() if len(mats) == 1 else torch.cat(mats)), None
+
     # -- device work --
     def _start(self, c: Cohort) -> None:
         torch = self.torch
@@ -329,21 +394,21 @@ class Engine:
         # are marked as used on the box stream for the caching allocator
         s.wait_stream(torch.cuda.current_stream(self.dev))
         with torch.cuda.stream(s):
-            vols = [r.volumes() if callable(r.volumes) else r.volumes for r in c.requests]
+            v, rows = self._cohort_volumes(c, s)
             starts = [r.starts() if callable(r.starts) else r.starts for r in c.requests]
-            for r, v, st in zip(c.requests, vols, starts):
-                if tuple(v.shape) != (r.n, c.box, c.box, c.box) or v.dtype != torch.float32:
-                    raise ValueError(f"request {r.rid}: volumes must be [{r.n}, {c.box}^3] float32")
+            for r, st in zip(c.requests, starts):
                 if tuple(st.shape) != (r.n, self.P, 3) or st.dtype != torch.float64:
                     raise ValueError(f"request {r.rid}: starts must be [{r.n}, {self.P}, 3] float64")
-                v.record_stream(s)
                 st.record_stream(s)
-            v = vols[0].contiguous() if len(vols) == 1 else torch.cat(vols)
             d = c.dev
             d["a"] = torch.empty((c.n, plan.C, 2), dtype=torch.float32, device=self.dev)
             d["a_bf16"] = torch.empty_like(d["a"])
-            plan.expand_ex(v, "bf16x3", out=d["a"], coarse=d["a_bf16"], batch_invariant=True)
-            del v, vols
+            if rows is None:
+                plan.expand_ex(v, "bf16x3", out=d["a"], coarse=d["a_bf16"], batch_invariant=True)
+            else:
+                plan.expand_rows(v, rows, "bf16x3", out=d["a"], coarse=d["a_bf16"],
+                                 batch_invariant=True)
+            del v, rows
             d["state"] = (starts[0].clone() if len(starts) == 1 else torch.cat(starts)).contiguous()
             d["tmpl"] = torch.cat([torch.full((r.n,), r.template, dtype=torch.int32, device=self.dev)
                                    for r in c.requests])

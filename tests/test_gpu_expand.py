@@ -222,3 +222,58 @@ def test_expand_bf16_modes():
     with pytest.raises(BhError):
         plan.expand_ex(dv, "bf16", coarse=coarse)
     plan.close()
+
+
+def test_expand_rows_in_place():
+    """bh_expand_rows reads vols[rows[b]] from a resident stack: in every
+    mode, batch-invariant or not, the same bits as the expansion of the
+    gathered copy (rows repeated and out of order, a ragged tile of 131
+    particles, a row offset into a wider coefficient array, the coarse
+    output); a row outside the stack gives NaN for that particle only and
+    BH_EINVAL from the plan's check, the others unchanged."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd._lib import BhError
+    dev = cuda_device()
+    N, L = 20, 8
+    rng = np.random.default_rng(33)
+    n_vols, B = 57, 131
+    stack = torch.from_numpy((rng.standard_normal((n_vols, N, N, N))).astype(np.float32)).to(dev)
+    rows_h = rng.integers(0, n_vols, B)
+    rows = torch.from_numpy(rows_h).to(dev)
+    copy = stack.index_select(0, rows).contiguous()
+    say(f"expand_rows N={N} L={L} n_vols={n_vols} B={B}")
+    plan = Plan(N, L, device=0)
+    C = plan.C
+    for mode in ("fp32", "bf16", "bf16x3"):
+        for inv in (False, True):
+            ref = plan.expand_ex(copy, mode, batch_invariant=inv)
+            got = plan.expand_rows(stack, rows, mode, batch_invariant=inv)
+            torch.cuda.synchronize()
+            assert torch.equal(got, ref), (mode, inv)
+    wide = torch.full((B, C + 5, 2), 7.0, dtype=torch.float32, device=dev)
+    coarse = torch.zeros_like(wide)
+    plan.expand_rows(stack, rows, "bf16x3", out=wide, coarse=coarse, batch_invariant=True)
+    ref_c = torch.empty((B, C, 2), dtype=torch.float32, device=dev)
+    ref = plan.expand_ex(copy, "bf16x3", coarse=ref_c, batch_invariant=True)
+    torch.cuda.synchronize()
+    assert torch.equal(wide[:, :C], ref) and torch.equal(coarse[:, :C], ref_c)
+    assert torch.all(wide[:, C:] == 7.0)
+    plan.check()
+    # a row outside the stack
+    bad = rows.clone()
+    bad[5] = n_vols
+    bad[9] = -1
+    got = plan.expand_rows(stack, bad, "fp32", batch_invariant=True)
+    ref = plan.expand_ex(copy, "fp32", batch_invariant=True)
+    torch.cuda.synchronize()
+    g = got.cpu().numpy()
+    assert np.all(np.isnan(g[[5, 9], :, 0]))       # (m = 0 imaginary parts are zero by layout)
+    keep = np.setdiff1d(np.arange(B), [5, 9])
+    np.testing.assert_array_equal(g[keep], ref.cpu().numpy()[keep])
+    with pytest.raises(BhError):
+        plan.check()
+    plan.check()                       # reported once
+    with pytest.raises((ValueError, TypeError)):
+        plan.expand_rows(stack, rows.to(torch.int32))
+    plan.close()

@@ -310,3 +310,56 @@ def test_engine_chooses_bands_by_energy_ratio():
     eng.drain()
     assert np.all(np.isfinite(r.score))
     plan.close()
+
+
+def test_served_rows_of_resident_stack():
+    """Requests naming rows of one resident stack (Rows, read in place by
+    the expansion; device and host indices) give the same bits as the same
+    volumes handed over as tensors, alone and in one cohort with tensor
+    requests (which then falls back to copying); a host index outside the
+    stack is refused at submission."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd.serving import Engine, Request, Rows
+    dev = cuda_device()
+    N = 24
+    L, bands = BOXES[N]
+    plan = Plan(N, L, device=0)
+    tmpl, blobs = _templates(plan, N)
+    vols = np.concatenate([_particles(blobs, N, t, 6, 300 + t)[0] for t in range(T_RES)])
+    stack = torch.from_numpy(vols).to(dev)
+    rng = np.random.default_rng(12)
+    spec = [(int(rng.integers(T_RES)), rng.integers(0, len(vols), int(n)))
+            for n in (5, 1, 9, 4, 7)]
+    starts = [torch.from_numpy(synth.serving.start_pool(len(ix), P, seed=70 + i)).to(dev)
+              for i, (_t, ix) in enumerate(spec)]
+    torch.cuda.synchronize()
+    say("serving: requests as rows of a resident stack")
+
+    def run(kinds):
+        eng = Engine({N: (L, bands)}, {N: tmpl}, restarts=P, steps=STEPS, plans={N: plan})
+        reqs = []
+        for (t, ix), st, kind in zip(spec, starts, kinds):
+            if kind == "tensor":
+                v = stack.index_select(0, torch.from_numpy(ix).to(dev))
+            elif kind == "rows_dev":
+                v = Rows(stack, torch.from_numpy(ix).to(dev))
+            else:
+                v = Rows(stack, ix)
+            reqs.append(eng.submit(Request(box=N, template=t, n=len(ix), volumes=v, starts=st)))
+        eng.drain()
+        return [(r.euler, r.score) for r in reqs]
+
+    base = run(["tensor"] * 5)
+    for kinds in (["rows_dev"] * 5, ["rows_host", "rows_dev", "rows_host", "rows_dev", "rows_dev"],
+                  ["rows_dev", "tensor", "rows_host", "tensor", "rows_dev"]):
+        got = run(kinds)
+        for (e0, s0), (e1, s1) in zip(base, got):
+            np.testing.assert_array_equal(e1, e0)
+            np.testing.assert_array_equal(s1, s0)
+    eng = Engine({N: (L, bands)}, {N: tmpl}, restarts=P, steps=STEPS, plans={N: plan})
+    with pytest.raises(ValueError):
+        eng.submit(Request(box=N, template=0, n=2, volumes=Rows(stack, np.array([0, len(vols)])),
+                           starts=starts[0][:2].contiguous()))
+    plan.check()
+    plan.close()
