@@ -708,7 +708,9 @@ static_assert(XRing<8>::kAhead == 7, "the wait table covers 0..7 younger blocks"
 
 // The four entries of a block for particle gq of the wave.  The reads are
 // written out, with their wait, because the compiler would otherwise wait
-// for every LDS-DMA load in flight before any read of the ring.
+// for every LDS-DMA load in flight before any read of the ring.  Every
+// output is early-clobber: a read's result may land while later reads of
+// the block still need their addresses.
 struct Block4 {
   double4 x[4];
 };
@@ -730,7 +732,7 @@ __device__ inline Block4 ring_block(const char* blk, int gq) {
       "ds_read_b128 %6, %14\n\t"
       "ds_read_b128 %7, %15\n\t"
       "s_waitcnt lgkmcnt(0)"
-      : "=v"(v0), "=v"(v1), "=v"(v2), "=v"(v3), "=v"(v4), "=v"(v5), "=v"(v6), "=v"(v7)
+      : "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3), "=&v"(v4), "=&v"(v5), "=&v"(v6), "=&v"(v7)
       : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7])
       : "memory");
   Block4 b;
