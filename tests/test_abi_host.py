@@ -64,6 +64,7 @@ def test_error_codes():
     assert L.bh_expand(None, None, 1, None, None) == _lib.BH_EINVAL
     assert L.bh_plan_num_coeffs(None, 0) == _lib.BH_EINVAL
     assert L.bh_expand_ex(None, None, 1, 0, None, None, None) == _lib.BH_EINVAL
+    assert L.bh_expand_rows(None, None, 4, None, 1, 0, None, 0, None, None) == _lib.BH_EINVAL
     assert L.bh_correlate_hess(None, None, None, 1, 0, None, 1, None, None, None, None) == _lib.BH_EINVAL
     assert L.bh_degree_energy(None, None, None, 1, 0, None, None) == _lib.BH_EINVAL
     o = _lib.AlignOpts()
