@@ -58,9 +58,12 @@ class Rows:
     """A request's particles as rows of a resident volume stack: particle i
     is stack[index[i]].  stack: [n_vols, N, N, N] float32 device tensor;
     index: [n] int64 tensor (device, or host: then range-checked at
-    submission).  The expansion reads the rows in place; a device index
-    outside the stack gives NaN results for those particles and BhError
-    (BH_EINVAL) from the engine's next library call on that box edge."""
+    submission and copied to the device asynchronously at admission).  The
+    expansion reads the rows in place, at admission on the engine's stream:
+    they must not change until the request's cohort has been admitted and
+    expanded (its results returned is a safe point).  A device index outside
+    the stack gives NaN results for those particles and BhError (BH_EINVAL)
+    from the engine's next library call on that box edge."""
     stack: object
     index: object
 
@@ -365,8 +368,10 @@ class Engine:
                 self._check_rows(r, v)
                 ix = v.index
                 if not (isinstance(ix, torch.Tensor) and ix.is_cuda):
-                    ix = torch.as_tensor(np.asarray(ix.cpu() if isinstance(ix, torch.Tensor)
-                                                    else ix, dtype=np.int64)).to(self.dev)
+                    # pinned staging, so the copy does not hold the host loop
+                    h = np.asarray(ix.cpu() if isinstance(ix, torch.Tensor) else ix,
+                                   dtype=np.int64)
+                    ix = torch.from_numpy(h).pin_memory().to(self.dev, non_blocking=True)
                 v = Rows(v.stack, ix.contiguous())
                 v.stack.record_stream(s)
                 v.index.record_stream(s)
