@@ -139,6 +139,7 @@ int get_band(bh_plan* p, int L, const DevBand** out) {
   d.L = L;
   d.n_classes = t.n_classes;
   d.n_entries = t.n_entries;
+  d.n_deg = (int)t.deg_off.size();
   int rc;
   if ((rc = upload_vec(t.rec, &d.rec)) != BH_OK ||
       (rc = upload_vec(t.sel, &d.sel)) != BH_OK ||

@@ -132,7 +132,8 @@ struct DevBand {
   int32_t* p_first = nullptr;   // [2L+2]
   int32_t* wave_p = nullptr;    // work split per wave count (BandTables::wave_p)
   int32_t* deg_start = nullptr; // [L+2]
-  int32_t* deg_off = nullptr;
+  int32_t* deg_off = nullptr;   // [n_deg]
+  int n_deg = 0;                // (l, k) pairs of the band
 };
 
 struct Buffer {

@@ -174,56 +174,87 @@ __global__ void k_band_weight(const float* __restrict__ a, int64_t lda,
 }
 
 // k_xi_classes and k_band_weight in one pass, one block per particle: the
-// band's particle coefficients (the first C(L), at most kXiLdsCoeffs) are
-// staged in LDS, the template's come through the cache.  Same sums in the
-// same order as the two kernels above.
-constexpr int kXiLdsCoeffs = 7680;   // 60 KB of (re, im) pairs (L <= 40)
+// band's particle and template coefficients (the first C(L) of each, at most
+// kXiLdsCoeffs) and the degree tables are staged in LDS, so an entry's sum
+// reads only LDS after its table entry; a thread keeps two entries in flight
+// and writes each entry's four weights as one 32-byte store.  Same sums in
+// the same order as the two kernels above.
+constexpr int kXiLdsCoeffs = 7680;   // (re, im) pairs of each operand (L <= 40)
+constexpr int kXiLdsDeg = 512;       // (l, k) pairs staged (279 at L = 40)
+
+// X1 = conj(b_m) a_n and X2 = conj(b_n) a_m summed over the entry's degree
+// terms, the products in FP64 from the FP32 coefficients.
+__device__ inline void xi_entry(const float2* sa, const float2* sb, const int32_t* sdeg_start,
+                                const int32_t* sdeg_off, int l, int m, int n, double& x1r,
+                                double& x1i, double& x2r, double& x2i) {
+  x1r = 0.0;
+  x1i = 0.0;
+  x2r = 0.0;
+  x2i = 0.0;
+  for (int i = sdeg_start[l]; i < sdeg_start[l + 1]; ++i) {
+    const int o = sdeg_off[i];
+    const float2 bm = sb[o + l + m], bn = sb[o + l + n], am = sa[o + l + m], an = sa[o + l + n];
+    const double bmr = bm.x, bmi = bm.y, bnr = bn.x, bni = bn.y;
+    const double amr = am.x, ami = am.y, anr = an.x, ani = an.y;
+    x1r += bmr * anr + bmi * ani;      // conj(b_m) a_n
+    x1i += bmr * ani - bmi * anr;
+    x2r += bnr * amr + bni * ami;      // conj(b_n) a_m
+    x2i += bnr * ami - bni * amr;
+  }
+}
 
 __global__ __launch_bounds__(512) void k_xi_band(
     const float* __restrict__ a, int64_t lda, const float* __restrict__ btab, int64_t ldt,
     const int32_t* __restrict__ tmpl, int n_tmpl, int64_t n_entries,
     const int32_t* __restrict__ sel, const double* __restrict__ wt,
-    const int32_t* __restrict__ deg_start, const int32_t* __restrict__ deg_off, int L, int CL,
-    double* __restrict__ X, double* __restrict__ Wb, int* bad) {
-  extern __shared__ float2 sa[];   // [CL]
+    const int32_t* __restrict__ deg_start, const int32_t* __restrict__ deg_off, int n_deg, int L,
+    int CL, double* __restrict__ X, double* __restrict__ Wb, int* bad) {
+  extern __shared__ float2 sa[];   // [2 CL]: the particle's coefficients, then the template's
   __shared__ double part[BH_MAX_L + 1];
+  __shared__ int32_t sdeg_start[BH_MAX_L + 2];
+  __shared__ int32_t sdeg_off[kXiLdsDeg];
+  float2* sb = sa + CL;
   const int tid = threadIdx.x;
   const int64_t pb = blockIdx.x;
   const int64_t ti = template_of(tmpl, n_tmpl, pb);
   const double nan = __builtin_nan("");
   const float2* ap = reinterpret_cast<const float2*>(a + pb * 2 * lda);
   const float2* b = reinterpret_cast<const float2*>(btab + (ti < 0 ? 0 : ti) * 2 * ldt);
-  for (int i = tid; i < CL; i += blockDim.x) sa[i] = ap[i];
+  for (int i = tid; i < CL; i += blockDim.x) {
+    sa[i] = ap[i];
+    sb[i] = b[i];
+  }
+  for (int i = tid; i <= L + 1; i += blockDim.x) sdeg_start[i] = deg_start[i];
+  for (int i = tid; i < n_deg; i += blockDim.x) sdeg_off[i] = deg_off[i];
   __syncthreads();
-  double* Xp = X + pb * n_entries * 4;
-  for (int64_t e = tid; e < n_entries; e += blockDim.x) {
-    const int l = sel[4 * e], m = sel[4 * e + 1], n = sel[4 * e + 2];
-    const double w1 = wt[2 * e], w2 = wt[2 * e + 1];
+  double4* Xp = reinterpret_cast<double4*>(X + pb * n_entries * 4);
+  const int stride = blockDim.x;
+  for (int64_t e0 = tid; e0 < n_entries; e0 += 2 * stride) {
+    const int64_t e1 = e0 + stride;
+    const bool has1 = e1 < n_entries;
+    const int4 s0 = reinterpret_cast<const int4*>(sel)[e0];
+    const int4 s1 = has1 ? reinterpret_cast<const int4*>(sel)[e1] : s0;
+    const double2 w0 = reinterpret_cast<const double2*>(wt)[e0];
+    const double2 w1 = has1 ? reinterpret_cast<const double2*>(wt)[e1] : w0;
     // a chain's padding entries (zero weights) are never read: not written
-    if (w1 == 0.0 && w2 == 0.0) continue;
-    double x1r = 0, x1i = 0, x2r = 0, x2i = 0;
-    for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
-      const int o = deg_off[i];
-      const float2 bm = b[o + l + m], bn = b[o + l + n], am = sa[o + l + m], an = sa[o + l + n];
-      const double bmr = bm.x, bmi = bm.y, bnr = bn.x, bni = bn.y;
-      const double amr = am.x, ami = am.y, anr = an.x, ani = an.y;
-      x1r += bmr * anr + bmi * ani;      // conj(b_m) a_n
-      x1i += bmr * ani - bmi * anr;
-      x2r += bnr * amr + bni * ami;      // conj(b_n) a_m
-      x2i += bnr * ami - bni * amr;
-    }
-    double* out = Xp + e * 4;
-    out[0] = ti < 0 ? nan : w1 * x1r;
-    out[1] = ti < 0 ? nan : w1 * x1i;
-    out[2] = ti < 0 ? nan : w2 * x2r;
-    out[3] = ti < 0 ? nan : w2 * x2i;
+    const bool live0 = w0.x != 0.0 || w0.y != 0.0;
+    const bool live1 = has1 && (w1.x != 0.0 || w1.y != 0.0);
+    double a0r, a0i, c0r, c0i, a1r, a1i, c1r, c1i;
+    xi_entry(sa, sb, sdeg_start, sdeg_off, s0.x, s0.y, s0.z, a0r, a0i, c0r, c0i);
+    xi_entry(sa, sb, sdeg_start, sdeg_off, s1.x, s1.y, s1.z, a1r, a1i, c1r, c1i);
+    if (live0)
+      Xp[e0] = ti < 0 ? double4{nan, nan, nan, nan}
+                      : double4{w0.x * a0r, w0.x * a0i, w0.y * c0r, w0.y * c0i};
+    if (live1)
+      Xp[e1] = ti < 0 ? double4{nan, nan, nan, nan}
+                      : double4{w1.x * a1r, w1.x * a1i, w1.y * c1r, w1.y * c1i};
   }
   for (int l = tid; l <= L; l += blockDim.x) {
     double na = 0.0, nb = 0.0;
-    for (int i = deg_start[l]; i < deg_start[l + 1]; ++i) {
-      const int o = deg_off[i];
+    for (int i = sdeg_start[l]; i < sdeg_start[l + 1]; ++i) {
+      const int o = sdeg_off[i];
       for (int m = -l; m <= l; ++m) {
-        const float2 av = sa[o + l + m], bv = b[o + l + m];
+        const float2 av = sa[o + l + m], bv = sb[o + l + m];
         const double ar = av.x, ai = av.y, br = bv.x, bi = bv.y;
         na += ar * ar + ai * ai;
         nb += br * br + bi * bi;
@@ -1066,6 +1097,24 @@ int launch_newton_split(int G, bh_plan* p, int64_t B, hipStream_t s, const DevBa
 
 // Class weights X of the band for B particles, and (Wb != NULL) the step
 // scale W_b of each.
+// k_xi_band stages two operands of up to kXiLdsCoeffs pairs in dynamic LDS
+// (120 KB at L = 40), above the default dynamic-LDS limit of a launch: the
+// limit is raised once per process (and device), else the two-kernel path
+// runs instead.
+bool xi_band_lds_ok() {
+  static thread_local int dev_ok[64] = {};   // 0 unknown, 1 ok, -1 refused
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  if (dev_ok[dev] == 0) {
+    const int bytes = 2 * kXiLdsCoeffs * (int)sizeof(float2);
+    const hipError_t e = hipFuncSetAttribute((const void*)k_xi_band,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    dev_ok[dev] = (e == hipSuccess) ? 1 : -1;
+    if (e != hipSuccess) (void)hipGetLastError();
+  }
+  return dev_ok[dev] > 0;
+}
+
 int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b,
                  const int32_t* tmpl, int n_tmpl, int64_t B, double** X, hipStream_t s,
                  int64_t lda = 0, int64_t ldt = 0, double* Wb = nullptr) {
@@ -1076,11 +1125,12 @@ int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b
   if (rc != BH_OK) return rc;
   *X = (double*)p->xi_scr.ptr;
   const int64_t CL = p->band_size[band.L];
-  if (Wb && CL <= kXiLdsCoeffs) {
+  if (Wb && CL <= kXiLdsCoeffs && band.n_deg <= kXiLdsDeg && xi_band_lds_ok()) {
     ProfScope ps(p, "xi_classes", s, B);
-    hipLaunchKernelGGL(k_xi_band, dim3((unsigned)B), dim3(512), (size_t)CL * sizeof(float2), s, a,
-                       lda, b, ldt, tmpl, n_tmpl, band.n_entries, band.sel, band.wt,
-                       band.deg_start, band.deg_off, band.L, (int)CL, *X, Wb, p->err_dev);
+    hipLaunchKernelGGL(k_xi_band, dim3((unsigned)B), dim3(512), (size_t)2 * CL * sizeof(float2), s,
+                       a, lda, b, ldt, tmpl, n_tmpl, band.n_entries, band.sel, band.wt,
+                       band.deg_start, band.deg_off, band.n_deg, band.L, (int)CL, *X, Wb,
+                       p->err_dev);
     BH_HIP(hipGetLastError());
     return BH_OK;
   }
