@@ -157,7 +157,7 @@ int bh_expand_into(bh_plan* p, const float* vols, int64_t B, int mode, float* co
 /* Expansion (Sec. II-A) of volumes picked by row from a resident stack,
  * read in place: particle b is volume rows[b] of vols.
  * vols:   dev float[n_vols][N][N][N]
- * rows:   dev int64[B], each in 0..n_vols-1 (repeats allowed)
+ * rows:   dev int64[B], 8-byte aligned, each in 0..n_vols-1 (repeats allowed)
  * coeffs, ldc, coarse, mode: as bh_expand_into (ldc == 0: C(L_max)).
  * The result for particle b is bit-identical to bh_expand_into on a copy
  * of vols[rows[b]] at position b (same mode, same B).  A row outside

@@ -487,6 +487,7 @@ int bh_expand_rows(bh_plan* p, const float* vols, int64_t n_vols, const int64_t*
     return set_error(BH_EINVAL, "a coarse output needs the BF16X3 mode");
   if (B == 0) return BH_OK;
   if (!vols || !rows || !coeffs) return set_error(BH_EINVAL, "NULL buffer");
+  if (((uintptr_t)rows & 7u) != 0) return set_error(BH_EINVAL, "row table not 8-byte aligned");
   return guarded([&]() -> int {
     DeviceGuard g(p->device);
     if (!g.ok) return set_error(BH_EDEVICE, "hipSetDevice failed");
