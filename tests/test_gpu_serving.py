@@ -363,3 +363,44 @@ def test_served_rows_of_resident_stack():
                            starts=starts[0][:2].contiguous()))
     plan.check()
     plan.close()
+
+
+def test_served_rows_device_index_outside_stack():
+    """A device Rows index outside the stack is caught on the device: that
+    particle's result is NaN, the request's other particles match the same
+    request with valid rows, and the plan reports BH_EINVAL (from a later
+    library call during the drain, or from Plan.check())."""
+    import torch
+    from paper_2509_01180_amd._lib import BhError
+    from paper_2509_01180_amd.api import Plan
+    from paper_2509_01180_amd.serving import Engine, Request, Rows
+    dev = cuda_device()
+    N = 24
+    L, bands = BOXES[N]
+    plan = Plan(N, L, device=0)
+    tmpl, blobs = _templates(plan, N)
+    stack = torch.from_numpy(_particles(blobs, N, 1, 5, 400)[0]).to(dev)
+    st = torch.from_numpy(synth.serving.start_pool(3, P, seed=90)).to(dev)
+    good = torch.tensor([0, 2, 4], dtype=torch.int64, device=dev)
+    bad = torch.tensor([0, 99, 4], dtype=torch.int64, device=dev)
+    say("serving: device Rows index outside the stack")
+    eng = Engine({N: (L, bands)}, {N: tmpl}, restarts=P, steps=STEPS, plans={N: plan})
+    r0 = eng.submit(Request(box=N, template=1, n=3, volumes=Rows(stack, good), starts=st))
+    eng.drain()
+    plan.check()
+    eng = Engine({N: (L, bands)}, {N: tmpl}, restarts=P, steps=STEPS, plans={N: plan})
+    r1 = eng.submit(Request(box=N, template=1, n=3, volumes=Rows(stack, bad), starts=st))
+    raised = False
+    try:
+        eng.drain()
+    except BhError:
+        raised = True
+        torch.cuda.synchronize()
+    if not raised:
+        with pytest.raises(BhError):
+            plan.check()
+        assert np.isnan(r1.score[1])
+        np.testing.assert_array_equal(r1.score[[0, 2]], r0.score[[0, 2]])
+        np.testing.assert_array_equal(r1.euler[[0, 2]], r0.euler[[0, 2]])
+    plan.check()                       # reported once
+    plan.close()
