@@ -147,8 +147,9 @@ def test_align_full_size_sampled():
 
 def test_align_band_beyond_staged_size():
     """A band of bandlimit 41 (C(41) = 7827 coefficients) takes the
-    unstaged cross-power path (bands up to 40 stage the particle's
-    coefficients in LDS); one band at 40 and one at 41 against the oracle."""
+    unstaged cross-power path (bands up to 40 stage the particle's and the
+    template's coefficients in LDS, 118 KB at 40); one band at 40 and one at
+    41 against the oracle."""
     from test_gpu_score import random_real_coeffs
     Lmax = 41
     idx = basis.IndexSet(Lmax)
