@@ -424,6 +424,17 @@ int bh_plan_set_tuning(bh_plan* p, int L, int waves, int persistent);
 int bh_profile_enable(bh_plan* p, int enable);
 int bh_profile_read(bh_plan* p, const char* name, int64_t* launches, double* total_ms,
                     int64_t* work);
+/* Wall time in milliseconds during which at least one recorded launch whose
+ * kernel name matches `name` (as bh_profile_read) was running: the union of
+ * their [start, stop] intervals, on whichever streams they ran (a march
+ * split over two streams overlaps its launches). */
+int bh_profile_busy(bh_plan* p, const char* name, double* busy_ms);
+
+/* Split eligible marches (bh_align, bh_align_t with the plain gradient
+ * march, at least 512 particles of 64 restarts, no graph capture) into two
+ * halves marched on two streams: streams 2 (the default) or 1 (never).
+ * Results are the same bits either way. */
+int bh_plan_set_march_streams(bh_plan* p, int streams);
 
 /* ---------------------------------------------------------------------
  * Reference kernels for hardware traffic counters (measurement only): a

@@ -79,6 +79,8 @@ SIGNATURES = {
     "bh_align_shifts": (_I, [_P, _P, _I64, _P, _I, _P, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P]),
     "bh_expand_into": (_I, [_P, _P, _I64, _I, _P, _I64, _P, _P]),
     "bh_expand_rows": (_I, [_P, _P, _I64, _P, _I64, _I, _P, _I64, _P, _P]),
+    "bh_profile_busy": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)]),
+    "bh_plan_set_march_streams": (_I, [_P, _I]),
     "bh_align_uneven": (_I, [_P, _P, _I64, _P, _P, _I64, _I, _P, _I64, ctypes.POINTER(AlignOpts),
                              _P, _P, _P, _P, _P, _P]),
     "bh_align_t": (_I, [_P, _P, _P, _I, _P, _I64, ctypes.POINTER(AlignOpts), _P, _P, _P, _P, _P, _P]),

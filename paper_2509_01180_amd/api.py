@@ -176,6 +176,18 @@ class Plan:
                                     ctypes.byref(w)), "bh_profile_read")
         return n.value, ms.value, w.value
 
+    def profile_busy(self, name: str) -> float:
+        """Milliseconds during which a recorded kernel named `name` was running
+        (the union over launches and streams; see bh_profile_busy)."""
+        ms = ctypes.c_double()
+        check(lib().bh_profile_busy(self._h, name.encode(), ctypes.byref(ms)), "bh_profile_busy")
+        return ms.value
+
+    def set_march_streams(self, streams: int) -> None:
+        """1: never split a march over two streams; 2 (default): split
+        eligible batches (see bh_plan_set_march_streams)."""
+        check(lib().bh_plan_set_march_streams(self._h, int(streams)), "bh_plan_set_march_streams")
+
     # ----------------------------------------------------------- calls --
     def expand(self, vols: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """vols [B, N, N, N] float32 -> coefficients [B, C(L_max), 2] float32."""

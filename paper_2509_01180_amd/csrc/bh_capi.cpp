@@ -8,6 +8,8 @@
 
 #include "bh_internal.h"
 
+#include <algorithm>
+
 namespace bh {
 
 namespace {
@@ -281,8 +283,12 @@ void bh_plan_destroy(bh_plan* p) {
                   (void*)p->csgn})
     if (q) (void)hipFree(q);
   for (Buffer* b : {&p->gathered, &p->partial, &p->xi_scr, &p->state_scr, &p->misc_scr,
-                    &p->prune_scr, &p->shift_scr, &p->newton_scr, &p->energy_scr})
+                    &p->prune_scr, &p->shift_scr, &p->newton_scr, &p->energy_scr, &p->xi_scr2,
+                    &p->state_scr2, &p->misc_scr2})
     if (b->ptr) (void)hipFree(b->ptr);
+  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+  if (p->join_ev) (void)hipEventDestroy(p->join_ev);
+  if (p->aux_stream) (void)hipStreamDestroy(p->aux_stream);
   for (auto& kv : p->bands) free_band(kv.second);
   if (p->err_host) (void)hipHostFree(p->err_host);
   p->prof.destroy();
@@ -385,6 +391,52 @@ int bh_profile_read(bh_plan* p, const char* name, int64_t* launches, double* tot
     if (launches) *launches = n;
     if (total_ms) *total_ms = ms;
     if (work) *work = w;
+    return BH_OK;
+  });
+}
+
+int bh_plan_set_march_streams(bh_plan* p, int streams) {
+  if (!p) return set_error(BH_EINVAL, "plan is NULL");
+  if (streams != 1 && streams != 2) return set_error(BH_EINVAL, "march streams must be 1 or 2");
+  p->march_streams = streams;
+  return BH_OK;
+}
+
+int bh_profile_busy(bh_plan* p, const char* name, double* busy_ms) {
+  if (!p || !name || !busy_ms) return set_error(BH_EINVAL, "NULL argument");
+  return guarded([&]() -> int {
+    DeviceGuard g(p->device);
+    std::string pat(name);
+    bool prefix = !pat.empty() && pat.back() == '*';
+    if (prefix) pat.pop_back();
+    // [start, stop] of every matching launch, in ms from the first one recorded
+    std::vector<std::pair<double, double>> iv;
+    const Profiler::Rec* ref = nullptr;
+    for (auto& r : p->prof.recs) {
+      const bool hit = prefix ? r.name.compare(0, pat.size(), pat) == 0 : r.name == pat;
+      if (!hit) continue;
+      BH_HIP(hipEventSynchronize(r.stop));
+      if (!ref) ref = &r;
+      float t0 = 0.0f, t1 = 0.0f;
+      BH_HIP(hipEventElapsedTime(&t0, ref->start, r.start));
+      BH_HIP(hipEventElapsedTime(&t1, ref->start, r.stop));
+      iv.push_back({(double)t0, (double)t1});
+    }
+    std::sort(iv.begin(), iv.end());
+    double busy = 0.0, lo = 0.0, hi = 0.0;
+    bool open = false;
+    for (const auto& x : iv) {
+      if (!open || x.first > hi) {
+        if (open) busy += hi - lo;
+        lo = x.first;
+        hi = x.second;
+        open = true;
+      } else if (x.second > hi) {
+        hi = x.second;
+      }
+    }
+    if (open) busy += hi - lo;
+    *busy_ms = busy;
     return BH_OK;
   });
 }

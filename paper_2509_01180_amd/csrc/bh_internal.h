@@ -186,6 +186,13 @@ struct bh_plan {
   int tuned_waves[BH_MAX_L + 1] = {};
   int tuned_persist[BH_MAX_L + 1] = {};   // 1: ascent launches as resident workgroups only
   std::map<int64_t, int> tuned_split[2];   // particle tiles -> split-K (FP32, BF16 GEMM)
+  // a march split into two halves on two streams (launch_align): the
+  // second half's scratch, its stream (default priority) and the fork and
+  // join events, created on first use; march_streams 1 never splits
+  bh::Buffer xi_scr2, state_scr2, misc_scr2;
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  int march_streams = 2;
 };
 
 namespace bh {

@@ -179,6 +179,7 @@ __global__ void k_band_weight(const float* __restrict__ a, int64_t lda,
 // reads only LDS after its table entry; a thread keeps two entries in flight
 // and writes each entry's four weights as one 32-byte store.  Same sums in
 // the same order as the two kernels above.
+constexpr int64_t kSplitMinHalf = 256;   // particles per half of a split march
 constexpr int kXiLdsCoeffs = 7680;   // (re, im) pairs of each operand (L <= 40)
 constexpr int kXiLdsDeg = 512;       // (l, k) pairs staged (279 at L = 40)
 
@@ -1117,13 +1118,14 @@ bool xi_band_lds_ok() {
 
 int prepare_band(bh_plan* p, const DevBand& band, const float* a, const float* b,
                  const int32_t* tmpl, int n_tmpl, int64_t B, double** X, hipStream_t s,
-                 int64_t lda = 0, int64_t ldt = 0, double* Wb = nullptr) {
+                 int64_t lda = 0, int64_t ldt = 0, double* Wb = nullptr, Buffer* xbuf = nullptr) {
   if (lda <= 0) lda = p->C;
   if (ldt <= 0) ldt = p->C;
+  if (!xbuf) xbuf = &p->xi_scr;
   // + kTablePad entries: the score loop reads up to three entries ahead
-  int rc = grow(p->xi_scr, ((size_t)B * band.n_entries + kTablePad) * 4 * sizeof(double));
+  int rc = grow(*xbuf, ((size_t)B * band.n_entries + kTablePad) * 4 * sizeof(double));
   if (rc != BH_OK) return rc;
-  *X = (double*)p->xi_scr.ptr;
+  *X = (double*)xbuf->ptr;
   const int64_t CL = p->band_size[band.L];
   if (Wb && CL <= kXiLdsCoeffs && band.n_deg <= kXiLdsDeg && xi_band_lds_ok()) {
     ProfScope ps(p, "xi_classes", s, B);
@@ -1213,22 +1215,24 @@ int launch_correlate(bh_plan* p, const DevBand& band, const float* a, const floa
   return BH_OK;
 }
 
-int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl, int n_tmpl,
-                 int64_t B, const bh_align_opts& o, const double* starts, double* euler_out,
-                 double* score_out, double* all_euler, double* all_score, hipStream_t s,
-                 int64_t lda, int64_t ldt, const int64_t* active) {
-  if (lda <= 0) lda = p->C;
-  if (ldt <= 0) ldt = p->C;
+namespace {
+// The march of launch_align for particles [0, B) of the given arrays, on
+// stream s with the given scratch (cross-power, restart state, step scales).
+int align_part(bh_plan* p, const float* a, const float* b, const int32_t* tmpl, int n_tmpl,
+               int64_t B, const bh_align_opts& o, const double* starts, double* euler_out,
+               double* score_out, double* all_euler, double* all_score, hipStream_t s,
+               int64_t lda, int64_t ldt, const int64_t* active, Buffer& xi_buf, Buffer& st_buf,
+               Buffer& misc_buf) {
   int P = o.n_restarts;
   const bool prune = o.n_keep > 0 && o.n_keep < P;
   const int K = prune ? o.n_keep : P;
   int rc;
-  if ((rc = grow(p->state_scr, (size_t)B * P * 4 * sizeof(double))) != BH_OK) return rc;
-  if ((rc = grow(p->misc_scr, (size_t)B * sizeof(double))) != BH_OK) return rc;
+  if ((rc = grow(st_buf, (size_t)B * P * 4 * sizeof(double))) != BH_OK) return rc;
+  if ((rc = grow(misc_buf, (size_t)B * sizeof(double))) != BH_OK) return rc;
   if (prune && (rc = grow(p->prune_scr, (size_t)B * K * 4 * sizeof(double))) != BH_OK) return rc;
-  double* state = (double*)p->state_scr.ptr;
+  double* state = (double*)st_buf.ptr;
   double* sscore = state + (size_t)B * P * 3;
-  double* Wb = (double*)p->misc_scr.ptr;
+  double* Wb = (double*)misc_buf.ptr;
   BH_HIP(hipMemcpyAsync(state, starts, (size_t)B * P * 3 * sizeof(double),
                         hipMemcpyDeviceToDevice, s));
   // bands are prepared first (host tables, uploads) so the loop only launches
@@ -1244,7 +1248,8 @@ int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl
     B = active ? active[bi] : B_all;     // the particles that take this band
     if (B == 0) continue;
     double* X = nullptr;
-    if ((rc = prepare_band(p, *band, a, b, tmpl, n_tmpl, B, &X, s, lda, ldt, Wb)) != BH_OK)
+    if ((rc = prepare_band(p, *band, a, b, tmpl, n_tmpl, B, &X, s, lda, ldt, Wb, &xi_buf)) !=
+        BH_OK)
       return rc;
     // lanes per particle: 64, or fewer when the (pruned) restarts fit
     const int G = P <= 8 ? 8 : (P <= 16 ? 16 : (P <= 32 ? 32 : 64));
@@ -1295,6 +1300,56 @@ int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl
     BH_HIP(hipMemcpyAsync(all_score, sscore, (size_t)B * P * sizeof(double),
                           hipMemcpyDeviceToDevice, s));
   return BH_OK;
+}
+}  // namespace
+
+// A batch's march is split into two halves marched on two streams (the
+// caller's and the plan's own, joined back to the caller's) when every
+// particle's result stays the same bits: the plain gradient march (no
+// pruning, Newton bands or per-band particle counts), 64 lanes per
+// particle, at least 256 particles in each half (the wave split does not
+// change), and the caller's stream not being captured into a graph.  A
+// band launch of a few hundred workgroups spends a good part of its time
+// in its first and last rounds; with two independent halves one half's
+// last round overlaps the other's middle.
+int launch_align(bh_plan* p, const float* a, const float* b, const int32_t* tmpl, int n_tmpl,
+                 int64_t B, const bh_align_opts& o, const double* starts, double* euler_out,
+                 double* score_out, double* all_euler, double* all_score, hipStream_t s,
+                 int64_t lda, int64_t ldt, const int64_t* active) {
+  if (lda <= 0) lda = p->C;
+  if (ldt <= 0) ldt = p->C;
+  const int P = o.n_restarts;
+  bool split = p->march_streams > 1 && !active && !(o.n_keep > 0 && o.n_keep < P) &&
+               o.newton_bands == 0 && P > 32 && B >= 2 * kSplitMinHalf;
+  if (split) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    BH_HIP(hipStreamIsCapturing(s, &cs));
+    split = cs == hipStreamCaptureStatusNone;
+  }
+  if (!split)
+    return align_part(p, a, b, tmpl, n_tmpl, B, o, starts, euler_out, score_out, all_euler,
+                      all_score, s, lda, ldt, active, p->xi_scr, p->state_scr, p->misc_scr);
+  if (!p->aux_stream) {
+    BH_HIP(hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking));
+    BH_HIP(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
+    BH_HIP(hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming));
+  }
+  const int64_t h = B / 2;
+  hipStream_t s2 = p->aux_stream;
+  BH_HIP(hipEventRecord(p->fork_ev, s));
+  BH_HIP(hipStreamWaitEvent(s2, p->fork_ev, 0));
+  int rc = align_part(p, a, b, tmpl, n_tmpl, h, o, starts, euler_out, score_out, all_euler,
+                      all_score, s, lda, ldt, nullptr, p->xi_scr, p->state_scr, p->misc_scr);
+  if (rc == BH_OK)
+    rc = align_part(p, a + (size_t)h * 2 * lda, b, tmpl ? tmpl + h : nullptr, n_tmpl, B - h, o,
+                    starts + (size_t)h * P * 3, euler_out + (size_t)h * 3, score_out + h,
+                    all_euler ? all_euler + (size_t)h * P * 3 : nullptr,
+                    all_score ? all_score + (size_t)h * P : nullptr, s2, lda, ldt, nullptr,
+                    p->xi_scr2, p->state_scr2, p->misc_scr2);
+  // the caller's stream waits for the second half whatever happened above
+  BH_HIP(hipEventRecord(p->join_ev, s2));
+  BH_HIP(hipStreamWaitEvent(s, p->join_ev, 0));
+  return rc;
 }
 
 namespace {

@@ -233,6 +233,9 @@ class Engine:
                 raise ValueError(f"plan for {N}^3 has L_max {plan.L_max}, not {L}")
             if max(bands) > L:
                 raise ValueError(f"bands of {N}^3 exceed its bandlimit {L}")
+            # the engine overlaps work across its own per-box streams; each
+            # band march stays on its box stream (no split over a plan stream)
+            plan.set_march_streams(1)
             self.plans[N] = plan
             self.streams[N] = torch.cuda.Stream(device=self.dev)
             specs[N] = BoxSpec(N, L, tuple(int(b) for b in bands),

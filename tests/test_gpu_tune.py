@@ -76,3 +76,46 @@ def test_persistent_launches_match():
     with pytest.raises(BhError):
         plan.set_tuning(6, 7, False)
     plan.close()
+
+
+def test_march_split_over_two_streams_same_bits():
+    """A march of 512 or more particles runs as two halves on two streams;
+    every particle's result (best and all restarts) is the same bits as with
+    the split off, for one template and for a template table (batch-invariant
+    form), and the profiler's busy time of the ascent launches is at most
+    the sum of their durations."""
+    import torch
+    from paper_2509_01180_amd.api import Plan
+    dev = cuda_device()
+    N, L, B, P = 16, 8, 600, 64
+    rng = np.random.default_rng(21)
+    bl = synth.blob_template(rng, 10)
+    vols = np.stack([synth.add_noise(synth.render_blobs(bl, N, g), 0.5, rng) for g in
+                     synth.quat_to_matrix(synth.haar_quaternions(rng, B))]).astype(np.float32)
+    starts = torch.from_numpy(synth.matrix_to_euler_zyz(synth.quat_to_matrix(
+        synth.haar_quaternions(rng, B * P))).reshape(B, P, 3)).to(dev)
+    say(f"two-stream march N={N} L={L} B={B}")
+    plan = Plan(N, L, device=0)
+    b = plan.expand(torch.from_numpy(synth.render_blobs(bl, N)[None].astype(np.float32)).to(dev))
+    a = plan.expand(torch.from_numpy(vols).to(dev))
+    tabs = torch.cat([b, 0.5 * b, b.flip(1)]).contiguous()
+    ti = torch.from_numpy(rng.integers(0, 3, B).astype(np.int32)).to(dev)
+    res = {}
+    for streams in (1, 2):
+        plan.set_march_streams(streams)
+        plan.profile(True)
+        r1 = plan.align(a, b[0].contiguous(), (4, 8), starts, 6, return_all=True)
+        r2 = plan.align_t(a, tabs, ti, (4, 8), starts, 6, return_all=True, batch_invariant=True)
+        torch.cuda.synchronize()
+        plan.profile(False)
+        n, ms, _w = plan.profile_read("march_L*")
+        busy = plan.profile_busy("march_L*")
+        assert 0.0 < busy <= ms * (1 + 1e-6)
+        assert n == (4 if streams == 1 else 8)
+        res[streams] = [x.cpu() for x in r1] + [x.cpu() for x in r2]
+    for x, y in zip(res[1], res[2]):
+        assert torch.equal(x, y)
+    assert np.all(np.isfinite(res[2][1].numpy()))
+    with pytest.raises(Exception):
+        plan.set_march_streams(3)
+    plan.close()
