@@ -348,10 +348,9 @@ int bh_plan_tuning(const bh_plan* p, int L, int64_t B, int* waves, int* persiste
   if (B < 1) return set_error(BH_EINVAL, "batch size out of range");
   if (waves) *waves = p->tuned_waves[L];
   if (persistent) *persistent = p->tuned_persist[L];
-  const int64_t mt = (B + kGemmBM - 1) / kGemmBM;
-  const int64_t nt = p->C_pad / kGemmBN, nk = p->VR_pad / kGemmBK;
-  if (split_f32) *split_f32 = expand_split(mt, nt, nk, false, &p->tuned_split[0]);
-  if (split_bf16) *split_bf16 = expand_split(mt, nt, nk, false, &p->tuned_split[1]);
+  DeviceGuard g(p->device);
+  if (split_f32) *split_f32 = expand_split_f32(p, B, false);
+  if (split_bf16) *split_bf16 = expand_split_bf16(p, B, false);
   return BH_OK;
 }
 

@@ -134,14 +134,17 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(const float* __restrict__ F
                                                      const float* __restrict__ Psi,
                                                      float* __restrict__ part, int64_t M_pad,
                                                      int64_t C_pad, int64_t VR_pad, ClassTiles ct,
-                                                     int nk, int nsplit) {
+                                                     int64_t nk_total, int nsplit) {
   __shared__ float As[2][BK][BM];
   __shared__ float Bs[2][BK][BN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t tm, tn, ts;
   gemm_tile(blockIdx.x, M_pad / BM, C_pad / BN, nsplit, tm, tn, ts);
   const int64_t m0 = tm * BM, n0 = tn * BN;
-  const int64_t k_begin = ts * nk * BK;
+  int64_t k0, nk64;
+  split_range(ts, nsplit, nk_total, k0, nk64);
+  const int nk = (int)nk64;
+  const int64_t k_begin = k0 * BK;
   const int lr = tid >> 5, lc = (tid & 31) * 4;
   const float* pa = Ft + class_of_tile(ct, tn) * VR_pad * M_pad + (k_begin + lr) * M_pad + m0 + lc;
   const float* pb = Psi + (k_begin + lr) * C_pad + n0 + lc;
@@ -240,8 +243,7 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
   const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
   const int64_t nk_total = p->VR_pad / BK;          // multiple of 16
-  const int nsplit = expand_split(mt, nt, nk_total, batch_invariant, &p->tuned_split[0]);
-  const int nk = (int)(nk_total / nsplit);
+  const int nsplit = expand_split_f32(p, B, batch_invariant);
   int rc;
   if ((rc = grow(p->gathered, (size_t)kParityClasses * p->VR_pad * M_pad * sizeof(float))) != BH_OK)
     return rc;
@@ -264,7 +266,7 @@ int launch_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, hipSt
   {
   ProfScope ps(p, "gemm", s, B);
   hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)(mt * nt * nsplit)), dim3(256), 0, s, Ft, p->psi,
-                     part, M_pad, p->C_pad, p->VR_pad, p->ctiles, nk, nsplit);
+                     part, M_pad, p->C_pad, p->VR_pad, p->ctiles, nk_total, nsplit);
   }
   BH_HIP(hipGetLastError());
   const int64_t tot = B * p->C;
@@ -331,7 +333,7 @@ int launch_expand_noalloc(bh_plan* p, const float* vols, int64_t B, float* coeff
     return set_error(BH_EUNSUPPORTED, "one 128-particle tile of this plan needs more than the " +
                                           std::to_string(BH_NOALLOC_SCRATCH_BYTES >> 20) +
                                           " MiB scratch");
-  const int64_t nt = p->C_pad / BN, nk = p->VR_pad / BK / nsplit;
+  const int64_t nt = p->C_pad / BN, nk_total = p->VR_pad / BK;
   const int64_t vol_stride = (int64_t)p->N * p->N * p->N;
   for (int64_t b0 = 0; b0 < B; b0 += tiles_per_pass * BM) {
     const int64_t nb = std::min(B - b0, tiles_per_pass * BM);
@@ -343,7 +345,7 @@ int launch_expand_noalloc(bh_plan* p, const float* vols, int64_t B, float* coeff
                        nullptr, p->vrep, p->VR, p->VR_pad, M_pad, p->N, Ft);
     BH_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)(mt * nt * nsplit)), dim3(256), 0, s, Ft,
-                       p->psi, part, M_pad, p->C_pad, p->VR_pad, p->ctiles, (int)nk, nsplit);
+                       p->psi, part, M_pad, p->C_pad, p->VR_pad, p->ctiles, nk_total, nsplit);
     BH_HIP(hipGetLastError());
     const int64_t tot = nb * p->C;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part,
@@ -352,6 +354,14 @@ int launch_expand_noalloc(bh_plan* p, const float* vols, int64_t B, float* coeff
     BH_HIP(hipGetLastError());
   }
   return BH_OK;
+}
+
+// q = 4: a tile's 64 KB of partial sums, written and read back, against the
+// chip-wide time of a K-step of 32 KB of operands (about 3.8 us per workgroup).
+int expand_split_f32(const bh_plan* p, int64_t B, bool batch_invariant) {
+  const int64_t mt = (B + BM - 1) / BM, nt = p->C_pad / BN, nk_total = p->VR_pad / BK;
+  return expand_split(mt, nt, nk_total, batch_invariant, &p->tuned_split[0],
+                      batch_invariant ? 0 : resident_workgroups(k_gemm_f32, 256), 4);
 }
 
 int tune_expand_f32(bh_plan* p, int64_t B, hipStream_t s) {
@@ -367,15 +377,14 @@ int tune_expand_f32(bh_plan* p, int64_t B, hipStream_t s) {
   BH_HIP(hipMemsetAsync(Ft, 0, fbytes, s));   // timing data: any finite values
   float best_ms = 1e30f;
   int best = 1;
-  for (int ns = 1; ns <= 16; ns *= 2) {
-    if (nk_total / ns < 8) break;
+  for (int ns = 1; ns <= 16; ++ns) {
+    if (ns > 1 && nk_total / ns < 8) break;
     float ms = 0.0f;
     rc = time_on_stream(
         s, 2, [] {},
         [&] {
           hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)(mt * nt * ns)), dim3(256), 0, s, Ft,
-                             p->psi, part, M_pad, p->C_pad, p->VR_pad, p->ctiles,
-                             (int)(nk_total / ns), ns);
+                             p->psi, part, M_pad, p->C_pad, p->VR_pad, p->ctiles, nk_total, ns);
         },
         &ms);
     if (rc != BH_OK) return rc;

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict
                                                       float* __restrict__ part_c,
                                                       float* __restrict__ part_r, int64_t M_pad,
                                                       int64_t C_pad, int64_t VR_pad, ClassTiles ct,
-                                                      int nk, int nsplit) {
+                                                      int64_t nk_total, int nsplit) {
   constexpr bool LO = CORR;
   using St = StepLds<LO>;
   __shared__ __attribute__((aligned(1024))) char smem[2 * St::bytes];
@@ -153,7 +153,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(const uint16_t* __restrict
   int64_t tm, tn, ts;
   gemm_tile(blockIdx.x, M_pad / BM, C_pad / BN, nsplit, tm, tn, ts);
   const int64_t m0 = tm * BM, n0 = tn * BN;
-  const int64_t k_begin = ts * (int64_t)nk * BK;
+  int64_t k0, nk64;
+  split_range(ts, nsplit, nk_total, k0, nk64);
+  const int nk = (int)nk64;
+  const int64_t k_begin = k0 * BK;
   const int64_t slab = class_of_tile(ct, tn) * M_pad * VR_pad;
   // DMA: wave w loads rows 32 w .. 32 w + 31 of each array as two blocks of
   // 16 rows; lane -> row 32 w + lane / 4 (+ 16), stored chunk lane % 4
@@ -303,8 +306,7 @@ int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, fl
   const int64_t M_pad = ((B + BM - 1) / BM) * BM;
   const int64_t mt = M_pad / BM, nt = p->C_pad / BN;
   const int64_t nk_total = p->VR_pad / BK;   // multiple of 16
-  const int nsplit = expand_split(mt, nt, nk_total, batch_invariant, &p->tuned_split[1]);
-  const int nk = (int)(nk_total / nsplit);
+  const int nsplit = expand_split_bf16(p, B, batch_invariant, refine);
   const size_t fbytes = (size_t)kParityClasses * M_pad * p->VR_pad * sizeof(uint16_t);
   const size_t pbytes = (size_t)nsplit * M_pad * p->C_pad * sizeof(float);
   if ((rc = grow(p->gathered, 2 * fbytes)) != BH_OK) return rc;
@@ -327,12 +329,12 @@ int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, fl
     const dim3 grid((unsigned)(mt * nt * nsplit));
     if (refine)
       hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, dim3(256), 0, s, fh, fl, p->psi_h,
-                         p->psi_l, part_c, part_r, M_pad, p->C_pad, p->VR_pad, p->ctiles, nk,
-                         nsplit);
+                         p->psi_l, part_c, part_r, M_pad, p->C_pad, p->VR_pad, p->ctiles,
+                         nk_total, nsplit);
     else
       hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, dim3(256), 0, s, fh, fl, p->psi_h,
-                         p->psi_l, part_c, part_c, M_pad, p->C_pad, p->VR_pad, p->ctiles, nk,
-                         nsplit);
+                         p->psi_l, part_c, part_c, M_pad, p->C_pad, p->VR_pad, p->ctiles,
+                         nk_total, nsplit);
   }
   BH_HIP(hipGetLastError());
   {
@@ -344,6 +346,19 @@ int launch_expand_bf16(bh_plan* p, const float* vols, int64_t B, bool refine, fl
   }
   BH_HIP(hipGetLastError());
   return BH_OK;
+}
+
+// q = 18: a tile's 128 KB of coarse and corrected partial sums, written and
+// read back, against the chip-wide time of a K-step (about 1.5 us per
+// workgroup); 9 for the coarse sums alone.
+int expand_split_bf16(const bh_plan* p, int64_t B, bool batch_invariant, bool refine) {
+  const int64_t mt = (B + BM - 1) / BM, nt = p->C_pad / BN, nk_total = p->VR_pad / BK;
+  int64_t slots = 0;
+  if (!batch_invariant)
+    slots = refine ? resident_workgroups(k_gemm_bf16<true, true>, 256)
+                   : resident_workgroups(k_gemm_bf16<true, false>, 256);
+  return expand_split(mt, nt, nk_total, batch_invariant, &p->tuned_split[1], slots,
+                      refine ? 18 : 9);
 }
 
 int tune_expand_bf16(bh_plan* p, int64_t B, hipStream_t s) {
@@ -362,8 +377,8 @@ int tune_expand_bf16(bh_plan* p, int64_t B, hipStream_t s) {
   BH_HIP(hipMemsetAsync(fh, 0, 2 * fbytes, s));   // timing data: any finite values
   float best_ms = 1e30f;
   int best = 1;
-  for (int ns = 1; ns <= 16; ns *= 2) {
-    if (nk_total / ns < 8) break;
+  for (int ns = 1; ns <= 16; ++ns) {
+    if (ns > 1 && nk_total / ns < 8) break;
     float ms = 0.0f;
     rc = time_on_stream(
         s, 2, [] {},
@@ -371,7 +386,7 @@ int tune_expand_bf16(bh_plan* p, int64_t B, hipStream_t s) {
           hipLaunchKernelGGL((k_gemm_bf16<true, true>), dim3((unsigned)(mt * nt * ns)), dim3(256),
                              0, s, fh, fl, p->psi_h, p->psi_l, part,
                              part + (size_t)ns * M_pad * p->C_pad, M_pad, p->C_pad, p->VR_pad,
-                             p->ctiles, (int)(nk_total / ns), ns);
+                             p->ctiles, nk_total, ns);
         },
         &ms);
     if (rc != BH_OK) return rc;

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -217,22 +218,84 @@ int get_band(bh_plan* p, int L, const DevBand** out);
 
 // launchers (return BH_OK or an error code)
 int build_basis(bh_plan* p);
-// Split-K factor of the expansion GEMM: doubled while the grid has fewer
-// than 2048 tiles (four waves of the 512 resident workgroups, so the last,
-// partial wave costs little) and each split keeps at least 8 K-steps.  With
-// batch_invariant the particle-tile count is taken as 8 (1024 particles)
-// whatever the batch, so a particle's sums never depend on the batch size.
+// Split-K factor of the expansion GEMM.
+//
+// Fixed rule: doubled while the grid has fewer than 2048 tiles and each
+// split keeps at least 8 K-steps.  With batch_invariant it is applied with
+// the particle-tile count taken as 8 (1024 particles) whatever the batch, so
+// a particle's sums never depend on the batch size.
+//
+// Otherwise a tuned factor if there is one.  Else, for grids of at most two
+// rounds of the `slots` resident workgroups, the factor ns (1..16, at least
+// 8 K-steps per split) with the smallest modelled cost in units of one
+// workgroup's K-step,
+//   ceil(tiles ns / slots) slots ceil(nk_total / ns) + ns tiles q,
+// the rounds (each as long as its longest split) plus the partial sums, q
+// being the HBM time of one tile's partial sums (written by the GEMM, read
+// back by the reduction) over the chip-wide time of one workgroup K-step
+// (ties to fewer splits).  Small batches gain most: at 64^3, L = 32 the fixed
+// rule's 16 splits of one or two particle tiles overflow one round by a few
+// workgroups.  Where the model's grid needs more rounds the fixed rule is
+// kept: its factors 4, 8 and 16 give each XCD whole K-slices (tiles are
+// placed split-major, XCD by XCD), which measured faster than the model's
+// fuller last round.  Splits need not divide nk_total: split s takes K-steps
+// [s nk_total / ns, (s + 1) nk_total / ns), the equal slices of the fixed
+// rule where ns divides nk_total.  Without a slot count (slots <= 0) the
+// fixed rule is used.
 inline int expand_split(int64_t mt, int64_t nt, int64_t nk_total, bool batch_invariant,
-                        const std::map<int64_t, int>* tuned = nullptr) {
-  if (batch_invariant) mt = 8;
-  if (tuned && !batch_invariant) {
+                        const std::map<int64_t, int>* tuned = nullptr, int64_t slots = 0,
+                        int64_t q = 0) {
+  if (!batch_invariant && tuned) {
     const auto it = tuned->find(mt);
     if (it != tuned->end()) return it->second;
   }
+  if (!batch_invariant && slots > 0) {
+    const int64_t tiles = mt * nt;
+    int best = 1;
+    int64_t best_cost = -1, best_rounds = 0;
+    for (int ns = 1; ns <= 16 && (ns == 1 || nk_total / ns >= 8); ++ns) {
+      const int64_t rounds = (tiles * ns + slots - 1) / slots;
+      const int64_t cost = rounds * slots * ((nk_total + ns - 1) / ns) + ns * tiles * q;
+      if (best_cost < 0 || cost < best_cost) {
+        best_cost = cost;
+        best = ns;
+        best_rounds = rounds;
+      }
+    }
+    if (best_rounds <= 2) return best;
+  }
+  if (batch_invariant) mt = 8;
   int nsplit = 1;
   while (nsplit < 16 && mt * nt * nsplit < 2048 && (nk_total / (nsplit * 2)) >= 8) nsplit *= 2;
   return nsplit;
 }
+// K-steps [k0, k0 + nk) of split ts of nsplit over nk_total steps.
+__host__ __device__ inline void split_range(int64_t ts, int64_t nsplit, int64_t nk_total,
+                                            int64_t& k0, int64_t& nk) {
+  k0 = ts * nk_total / nsplit;
+  nk = (ts + 1) * nk_total / nsplit - k0;
+}
+// Workgroups of a kernel that fit on the current device at once (0 if
+// unknown), cached per kernel.
+template <typename K>
+int64_t resident_workgroups(K kernel, int threads) {
+  static std::mutex mu;
+  static std::map<const void*, int64_t> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = cache.find((const void*)kernel);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return cache[(const void*)kernel] = (int64_t)per_cu * cus;
+}
+// The split-K factors the FP32 and split-BF16 expansions use for B particles
+// (each GEMM's resident workgroups on the current device as the slots;
+// refine: the split-BF16 GEMM with the correction products).
+int expand_split_f32(const bh_plan* p, int64_t B, bool batch_invariant);
+int expand_split_bf16(const bh_plan* p, int64_t B, bool batch_invariant, bool refine = true);
 // Integer voxel shifts, passed to kernels by value.
 constexpr int kMaxShifts = 125;
 struct ShiftTable {

@@ -990,23 +990,6 @@ void launch_correlate_any(int W, bh_plan* p, dim3 grid, hipStream_t s, const Dev
   }
 }
 
-// Workgroups of a kernel that fit on the device at once (0 if unknown),
-// cached per kernel.
-template <typename K>
-int64_t resident_workgroups(K kernel, int threads) {
-  static std::mutex mu;
-  static std::map<const void*, int64_t> cache;
-  std::lock_guard<std::mutex> lock(mu);
-  const auto it = cache.find((const void*)kernel);
-  if (it != cache.end()) return it->second;
-  int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
-      hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return 0;
-  return cache[(const void*)kernel] = (int64_t)per_cu * cus;
-}
-
 template <int W, bool NEWTON, int G>
 void launch_march_w(bh_plan* p, int64_t B, hipStream_t s, const DevBand& band, const double* X,
                     const double* Wb, int P, int steps, const bh_align_opts& o, double* state,

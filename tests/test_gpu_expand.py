@@ -35,18 +35,25 @@ def run_gpu(N, L, vols, with_split=False):
     return (got, split) if with_split else got
 
 
-def fp32_terms(N, nsplit):
-    """Rounding steps on the way to one FP32 coefficient: the 8-image fold
-    (three levels of additions), the basis entry's FP32 storage, the longest
-    run of sequential FP32 accumulations in one split-K slice (the folded
-    voxel count, padded to 512, over the splits) and the sum of the splits."""
+def k_steps(N):
+    """K-steps of 32 folded voxels of an N^3 plan: one representative per
+    mirror orbit inside the ball, the count padded to 512."""
     i = np.arange(N)
     x = (i - (N - 1) / 2) * 2 / N
     half = x[x >= -1e-12]          # one representative per mirror orbit (and the planes)
     X, Y, Z = np.meshgrid(half, half, half, indexing="ij")
     VR = int(((X ** 2 + Y ** 2 + Z ** 2) < 1).sum())
-    VR_pad = -(-VR // 512) * 512
-    return 3 + 1 + VR_pad // nsplit + nsplit
+    return -(-VR // 512) * 512 // 32
+
+
+def fp32_terms(N, nsplit):
+    """Rounding steps on the way to one FP32 coefficient: the 8-image fold
+    (three levels of additions), the basis entry's FP32 storage, the longest
+    run of sequential FP32 accumulations in one split-K slice (the longest
+    split's K-steps of 32 folded voxels, the count padded to 512) and the sum
+    of the splits."""
+    longest = -(-k_steps(N) // nsplit) * 32     # the longest split's K-steps of 32 voxels
+    return 3 + 1 + longest + nsplit
 
 
 def assert_fp32_per_coefficient(got, ref, vols, L, nsplit):
@@ -218,6 +225,11 @@ def test_expand_bf16_modes():
     print(f"normwise error: bf16 {e1}, bf16x3 {e3}, fp32 {e32}")
     assert np.all(e1 <= 5e-3) and np.all(e1 >= 1e-5)     # genuinely BF16
     assert np.all(e3 <= 1e-5)
+    # at 200 particles the split-K factor leaves K-step slices of unequal
+    # length (split s takes steps [s n / ns, (s + 1) n / ns))
+    split = plan.tuning(B)["split_f32"]
+    assert k_steps(w.N) % split != 0 and k_steps(w.N) % plan.tuning(B)["split_bf16"] != 0
+    assert_fp32_per_coefficient(to_complex(c32)[sample], ref, vols[sample], w.L_max, split)
     np.testing.assert_allclose(coarse.cpu().numpy(), c1.cpu().numpy(), rtol=0, atol=1e-6 * float(c1.abs().max()))
     with pytest.raises(BhError):
         plan.expand_ex(dv, "bf16", coarse=coarse)

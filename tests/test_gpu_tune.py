@@ -33,7 +33,7 @@ def test_autotune_choices_and_results():
     got = plan.autotune(B, (8, 16), restarts=P)
     print("tuned", got)
     assert all(w in (4, 5, 6, 8, 10, 12, 16) for w in got["waves"].values())
-    assert got["split_f32"] in (1, 2, 4, 8, 16) and got["split_bf16"] in (1, 2, 4, 8, 16)
+    assert 1 <= got["split_f32"] <= 16 and 1 <= got["split_bf16"] <= 16
     a1 = plan.expand(v)
     e1, s1 = plan.align(a1, b.contiguous(), (8, 16), starts, 10)
     torch.cuda.synchronize()
