@@ -78,8 +78,8 @@ def score_kernel_sources_hash() -> str:
 
 
 def load_traffic(kernel_hash: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    """HBM bytes per band (its two half-launches) from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "march_traffic.json")
     if not os.path.exists(path):
         return None
@@ -89,7 +89,7 @@ def load_traffic(kernel_hash: str):
         return None
     if d.get("kernel_source_hash") != kernel_hash:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("hbm_bytes_per_band")
 
 
 def orbit_representatives(N: int) -> int:
