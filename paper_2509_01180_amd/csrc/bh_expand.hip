@@ -221,11 +221,23 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ part, 
   if (t >= B * C) return;
   const int64_t b = t / C, q = t % C;
   const int32_t sr = csrc[2 * q], si = csrc[2 * q + 1];
+  // every split's loads first (in flight together), then the sums in split order
+  float vr[kMaxSplit], vi[kMaxSplit];
+#pragma unroll
+  for (int s = 0; s < kMaxSplit; ++s) {
+    if (s < nsplit) {
+      const float* ps = part + (int64_t)s * M_pad * C_pad + b * C_pad;
+      vr[s] = ps[sr];
+      vi[s] = si >= 0 ? ps[si] : 0.0f;
+    }
+  }
   float re = 0.0f, im = 0.0f;
-  for (int s = 0; s < nsplit; ++s) {
-    const float* ps = part + (int64_t)s * M_pad * C_pad + b * C_pad;
-    re += ps[sr];
-    if (si >= 0) im += ps[si];
+#pragma unroll
+  for (int s = 0; s < kMaxSplit; ++s) {
+    if (s < nsplit) {
+      re += vr[s];
+      im += vi[s];
+    }
   }
   const int64_t o = b * ldc + q;
   coeffs[2 * o] = re * csgn[2 * q];
@@ -377,7 +389,7 @@ int tune_expand_f32(bh_plan* p, int64_t B, hipStream_t s) {
   BH_HIP(hipMemsetAsync(Ft, 0, fbytes, s));   // timing data: any finite values
   float best_ms = 1e30f;
   int best = 1;
-  for (int ns = 1; ns <= 16; ++ns) {
+  for (int ns = 1; ns <= kMaxSplit; ++ns) {
     if (ns > 1 && nk_total / ns < 8) break;
     float ms = 0.0f;
     rc = time_on_stream(

@@ -256,14 +256,26 @@ __global__ __launch_bounds__(256) void k_reduce2(const float* __restrict__ part_
   if (t >= B * C) return;
   const int64_t b = t / C, q = t % C;
   const int32_t sr = csrc[2 * q], si = csrc[2 * q + 1];
+  // every split's loads first (in flight together), then the sums in split order
+  float vcr[kMaxSplit], vci[kMaxSplit], vrr[kMaxSplit], vri[kMaxSplit];
+#pragma unroll
+  for (int s = 0; s < kMaxSplit; ++s) {
+    if (s < nsplit) {
+      const int64_t o = (int64_t)s * M_pad * C_pad + b * C_pad;
+      vcr[s] = part_c[o + sr];
+      vci[s] = si >= 0 ? part_c[o + si] : 0.0f;
+      vrr[s] = part_r ? part_r[o + sr] : 0.0f;
+      vri[s] = (part_r && si >= 0) ? part_r[o + si] : 0.0f;
+    }
+  }
   float cre = 0.0f, cim = 0.0f, rre = 0.0f, rim = 0.0f;
-  for (int s = 0; s < nsplit; ++s) {
-    const int64_t o = (int64_t)s * M_pad * C_pad + b * C_pad;
-    cre += part_c[o + sr];
-    if (si >= 0) cim += part_c[o + si];
-    if (part_r) {
-      rre += part_r[o + sr];
-      if (si >= 0) rim += part_r[o + si];
+#pragma unroll
+  for (int s = 0; s < kMaxSplit; ++s) {
+    if (s < nsplit) {
+      cre += vcr[s];
+      cim += vci[s];
+      rre += vrr[s];
+      rim += vri[s];
     }
   }
   const float gr = csgn[2 * q], gi = csgn[2 * q + 1];
@@ -377,7 +389,7 @@ int tune_expand_bf16(bh_plan* p, int64_t B, hipStream_t s) {
   BH_HIP(hipMemsetAsync(fh, 0, 2 * fbytes, s));   // timing data: any finite values
   float best_ms = 1e30f;
   int best = 1;
-  for (int ns = 1; ns <= 16; ++ns) {
+  for (int ns = 1; ns <= kMaxSplit; ++ns) {
     if (ns > 1 && nk_total / ns < 8) break;
     float ms = 0.0f;
     rc = time_on_stream(

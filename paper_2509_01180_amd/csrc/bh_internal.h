@@ -242,6 +242,7 @@ int build_basis(bh_plan* p);
 // [s nk_total / ns, (s + 1) nk_total / ns), the equal slices of the fixed
 // rule where ns divides nk_total.  Without a slot count (slots <= 0) the
 // fixed rule is used.
+constexpr int kMaxSplit = 16;   // split-K factors 1..16 (the reductions hold one value per split)
 inline int expand_split(int64_t mt, int64_t nt, int64_t nk_total, bool batch_invariant,
                         const std::map<int64_t, int>* tuned = nullptr, int64_t slots = 0,
                         int64_t q = 0) {
@@ -253,7 +254,7 @@ inline int expand_split(int64_t mt, int64_t nt, int64_t nk_total, bool batch_inv
     const int64_t tiles = mt * nt;
     int best = 1;
     int64_t best_cost = -1, best_rounds = 0;
-    for (int ns = 1; ns <= 16 && (ns == 1 || nk_total / ns >= 8); ++ns) {
+    for (int ns = 1; ns <= kMaxSplit && (ns == 1 || nk_total / ns >= 8); ++ns) {
       const int64_t rounds = (tiles * ns + slots - 1) / slots;
       const int64_t cost = rounds * slots * ((nk_total + ns - 1) / ns) + ns * tiles * q;
       if (best_cost < 0 || cost < best_cost) {
@@ -266,7 +267,8 @@ inline int expand_split(int64_t mt, int64_t nt, int64_t nk_total, bool batch_inv
   }
   if (batch_invariant) mt = 8;
   int nsplit = 1;
-  while (nsplit < 16 && mt * nt * nsplit < 2048 && (nk_total / (nsplit * 2)) >= 8) nsplit *= 2;
+  while (nsplit < kMaxSplit && mt * nt * nsplit < 2048 && (nk_total / (nsplit * 2)) >= 8)
+    nsplit *= 2;
   return nsplit;
 }
 // K-steps [k0, k0 + nk) of split ts of nsplit over nk_total steps.
