@@ -141,8 +141,9 @@ int bh_expand(bh_plan* p, const float* vols, int64_t B, float* coeffs, void* str
  * first BF16 call and kept by the plan.
  * Adding BH_EXPAND_BATCH_INVARIANT to the mode fixes the summation order of
  * each particle's coefficients independently of B (a particle expanded
- * alone or in any batch gives the same bits); otherwise small batches split
- * the voxel sum further to fill the GPU. */
+ * alone or in any batch gives the same bits); otherwise the voxel sum is cut
+ * into 1..16 slices (split-K) by a rule of the batch size, more for small
+ * batches, so that the GEMM's workgroups fill the GPU. */
 enum { BH_EXPAND_FP32 = 0, BH_EXPAND_BF16 = 1, BH_EXPAND_BF16X3 = 2,
        BH_EXPAND_BATCH_INVARIANT = 16 };
 int bh_expand_ex(bh_plan* p, const float* vols, int64_t B, int mode, float* coeffs, float* coarse,
