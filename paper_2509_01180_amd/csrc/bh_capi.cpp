@@ -421,21 +421,7 @@ int bh_profile_busy(bh_plan* p, const char* name, double* busy_ms) {
       BH_HIP(hipEventElapsedTime(&t1, ref->start, r.stop));
       iv.push_back({(double)t0, (double)t1});
     }
-    std::sort(iv.begin(), iv.end());
-    double busy = 0.0, lo = 0.0, hi = 0.0;
-    bool open = false;
-    for (const auto& x : iv) {
-      if (!open || x.first > hi) {
-        if (open) busy += hi - lo;
-        lo = x.first;
-        hi = x.second;
-        open = true;
-      } else if (x.second > hi) {
-        hi = x.second;
-      }
-    }
-    if (open) busy += hi - lo;
-    *busy_ms = busy;
+    *busy_ms = interval_union(std::move(iv));
     return BH_OK;
   });
 }

@@ -262,4 +262,23 @@ BandTables band_tables(int L, int Lmax) {
   return t;
 }
 
+double interval_union(std::vector<std::pair<double, double>> iv) {
+  std::sort(iv.begin(), iv.end());
+  double busy = 0.0, lo = 0.0, hi = 0.0;
+  bool open = false;
+  for (const auto& x : iv) {
+    if (x.second < x.first) continue;
+    if (!open || x.first > hi) {
+      if (open) busy += hi - lo;
+      lo = x.first;
+      hi = x.second;
+      open = true;
+    } else if (x.second > hi) {
+      hi = x.second;
+    }
+  }
+  if (open) busy += hi - lo;
+  return busy;
+}
+
 }  // namespace bh

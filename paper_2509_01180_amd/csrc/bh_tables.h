@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 namespace bh {
@@ -104,5 +105,10 @@ int64_t wave_block_offset(int L, int W);
 
 // Tables of band L; coefficient offsets refer to the layout of index_set(Lmax).
 BandTables band_tables(int L, int Lmax);
+
+// Total length of the union of closed intervals [first, second] (in any
+// order; intervals that touch or overlap count once; second < first counts
+// as empty).  The busy time of kernel launches that overlap on two streams.
+double interval_union(std::vector<std::pair<double, double>> iv);
 
 }  // namespace bh

@@ -1,11 +1,14 @@
 // Host-side checks of the library's table builders (Bessel zeros, index
-// sets, band tables of the Wigner recurrence, work splits, ball voxels),
+// sets, band tables of the Wigner recurrence, work splits, ball voxels, the
+// union of launch intervals),
 // built with the address and undefined-behaviour sanitizers and bounds-
 // checked standard containers by tests/test_host_sanitize.py.  Prints one
 // line per failed invariant and exits non-zero if any failed.
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <set>
+#include <utility>
 #include <vector>
 
 #include "bh_tables.h"
@@ -141,7 +144,45 @@ static void check_voxels(int N) {
   for (int32_t v : rep) CHECK(in.count(v) == 1, "N=%d: representative %d outside the ball", N, v);
 }
 
+// interval_union against its definition: exact sums for disjoint, nested,
+// touching and reversed intervals, and a brute-force count on a grid for
+// random intervals with endpoints on that grid.
+static void check_interval_union() {
+  using V = std::vector<std::pair<double, double>>;
+  CHECK(interval_union(V{}) == 0.0, "empty union");
+  CHECK(interval_union(V{{1, 2}, {3, 5}}) == 3.0, "disjoint");
+  CHECK(interval_union(V{{3, 5}, {1, 2}}) == 3.0, "disjoint, unsorted");
+  CHECK(interval_union(V{{0, 10}, {2, 3}, {4, 9}}) == 10.0, "nested");
+  CHECK(interval_union(V{{0, 2}, {2, 4}}) == 4.0, "touching");
+  CHECK(interval_union(V{{0, 3}, {1, 4}, {2, 5}}) == 5.0, "overlapping chain");
+  CHECK(interval_union(V{{1, 1}, {2, 2}}) == 0.0, "points");
+  CHECK(interval_union(V{{5, 4}, {0, 1}}) == 1.0, "reversed interval");
+  uint64_t z = 88172645463325252ull;
+  auto next = [&](int m) {
+    z ^= z << 13;
+    z ^= z >> 7;
+    z ^= z << 17;
+    return (int)(z % (uint64_t)m);
+  };
+  for (int t = 0; t < 200; ++t) {
+    const int n = next(12), G = 64;
+    V iv;
+    std::vector<char> cover(G, 0);   // cell [g, g + 1) covered
+    for (int i = 0; i < n; ++i) {
+      int a = next(G + 1), b = next(G + 1);
+      if (a > b) std::swap(a, b);
+      iv.push_back({a / 8.0, b / 8.0});
+      for (int g = a; g < b; ++g) cover[g] = 1;
+    }
+    int cells = 0;
+    for (char c : cover) cells += c;
+    CHECK(interval_union(iv) == cells / 8.0, "random case %d: %g against %g", t,
+          interval_union(iv), cells / 8.0);
+  }
+}
+
 int main() {
+  check_interval_union();
   for (int L = 0; L <= 64; ++L) check_index_set(L);
   for (int L : {0, 1, 2, 3, 4, 7, 8, 11, 16, 24, 32, 40, 41, 42, 64}) check_band(L, L);
   check_band(8, 32);

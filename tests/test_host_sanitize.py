@@ -1,5 +1,5 @@
 """The host table builders (bh_tables.cpp: Bessel zeros, index sets, band
-tables, work splits, voxel lists) under AddressSanitizer and
+tables, work splits, voxel lists, the union of launch intervals) under AddressSanitizer and
 UndefinedBehaviorSanitizer with bounds-checked standard containers, built
 with g++ for the host only (no GPU code), and their invariants checked
 (tests/host/tables_check.cpp)."""
